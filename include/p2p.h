@@ -1,0 +1,148 @@
+/*
+ * p2p.h - C ABI of the MI355X near-field P2P operator.
+ *
+ * The operator is the near-field part of the MLFMA matrix-vector product (the
+ * paper's section 1 splits the product into a directly computed near field, the
+ * P2P operator, and a hierarchical far field).  Points are grouped into the
+ * boxes of the last tree level (section 3.1); every target receives, from every
+ * source in its own and the adjacent boxes (sections 3.2 and 3.3; 27 boxes in
+ * three dimensions), the kernel value times the source strength:
+ *
+ *     y[i,c] = sum_{j ~ i, x_j != x_i}  G(|x_i - x_j|) q[j,c],
+ *     G(r)   = exp(i k r) / (4 pi r)        (k = 0: the Laplace kernel),
+ *     i ~ j  <=>  max_a |b_i[a] - b_j[a]| <= 1  for the integer leaf-box ids b.
+ *
+ * The near relation is defined by the ids, not by the positions.  Pairs at
+ * distance zero (the self pair and coincident points) are skipped.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are HIP device pointers, except p2p_plan_export's outputs
+ *    and p2p_box_ids' origin, which are host memory.
+ *  - xyz is [n,3] row-major float64.  box_ijk is [n,3] row-major int32, each id
+ *    in [0, 2^21).  q, y and gradients are [n, nrhs] row-major complex numbers
+ *    with interleaved (re, im) parts, complex64 (P2P_C64) or complex128
+ *    (P2P_C128), in the caller's original point order.
+ *  - The caller owns every array it passes.  A plan owns the device memory it
+ *    allocates and frees it in p2p_plan_destroy.
+ *  - stream is a hipStream_t (NULL: the legacy default stream).  Work is
+ *    enqueued on it.  p2p_plan_create waits for its own work before returning;
+ *    the other calls return as soon as their work is enqueued.
+ *  - A call returns a status and never aborts.  On error no output is written
+ *    (for asynchronous calls: no work is enqueued) and p2p_last_error() returns
+ *    a message for the calling thread.
+ *  - p2p_apply and p2p_apply_backward allocate nothing and do not synchronise,
+ *    so they may be captured in a HIP graph.  They use scratch memory owned by
+ *    the plan: calls on one plan must be ordered (one stream at a time).
+ */
+#ifndef P2P_H
+#define P2P_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p2p_plan_s* p2p_plan;
+
+typedef enum {
+  P2P_OK = 0,
+  P2P_ERR_ARG = 1,   /* null pointer, negative size, bad option value            */
+  P2P_ERR_RANGE = 2, /* id outside [0, 2^21), non-finite coordinate, bad k or h  */
+  P2P_ERR_DTYPE = 3, /* complex type differs from the plan's precision            */
+  P2P_ERR_NOMEM = 4, /* device allocation failed                                  */
+  P2P_ERR_HIP = 5,   /* a HIP runtime call failed                                 */
+  P2P_ERR_STATE = 6  /* plan handle invalid (null or destroyed)                   */
+} p2p_status;
+
+typedef enum {
+  P2P_C64 = 1,  /* complex64 strengths, FP32 arithmetic (fixed-point differences) */
+  P2P_C128 = 2  /* complex128 strengths, FP64 arithmetic                          */
+} p2p_dtype;
+
+typedef enum {
+  /* Per target box, one contiguous SoA list holding every source of its
+   * neighbourhood (the redundant layout of the paper's section 3.3, kept per box). */
+  P2P_LAYOUT_TILES = 0,
+  /* No replicated sources: each box walks its neighbour boxes' ranges of the
+   * sorted point arrays (the non-redundant, indexed layout of section 3.2).     */
+  P2P_LAYOUT_CSR = 1
+} p2p_layout;
+
+typedef struct {
+  p2p_dtype precision; /* arithmetic of p2p_apply / p2p_apply_backward             */
+  p2p_layout layout;
+  int32_t max_rhs;     /* largest nrhs accepted by apply and backward (>= 1)        */
+  uint32_t flags;      /* reserved, must be 0                                      */
+} p2p_opts;
+
+typedef struct {
+  int64_t n_points;
+  int64_t n_boxes;      /* non-empty leaf boxes B                                  */
+  int64_t n_nbr;        /* entries of the neighbour lists, sum over boxes          */
+  int64_t n_slots;      /* sum over targets of the neighbourhood's source count    */
+  int64_t n_pairs;      /* ordered near pairs with r != 0 (interactions per RHS)   */
+  int64_t n_zero_pairs; /* near pairs skipped because r == 0 (self pairs included) */
+  int64_t tile_entries; /* length of the replicated source lists (TILES), else 0   */
+  int64_t device_bytes; /* device memory held by the plan                          */
+  int32_t t_max;        /* largest box occupancy t                                 */
+  int32_t quantum_exp;  /* FP32 plans: coordinates are integers in units of 2^e    */
+  double d_mean;        /* n_points / n_boxes                                      */
+  double max_sep;       /* largest per-axis coordinate difference of a near pair   */
+} p2p_info;
+
+/* Leaf-box ids from positions: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h),
+ * evaluated in FP64 with a correctly rounded subtraction and division (paper
+ * section 3.1: the points are assigned to the boxes of the last level).
+ * origin: host double[3].  Returns P2P_ERR_RANGE (and writes nothing) if a
+ * coordinate is not finite or an id falls outside [0, 2^21).  Synchronises stream. */
+p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
+                       void* stream);
+
+/* Builds the plan of one point set (paper sections 3.1-3.3: boxes in Morton order,
+ * neighbour lists, and the per-box source lists): Morton keys of the ids, a stable
+ * sort of the points by key, the table of non-empty boxes, the 27-neighbour lists
+ * (each sorted by key) and, for P2P_LAYOUT_TILES, the replicated per-box source
+ * lists.  Morton key: bit 3b is bit b of the x id, 3b+1 of y, 3b+2 of z.
+ * n = 0 gives a valid empty plan.  k must be finite and >= 0.  opts may be NULL
+ * (complex64, tiles, max_rhs 1).  Copies what it needs from xyz and box_ijk.
+ * Synchronises stream.  On success *out holds the plan. */
+p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n, double k, const p2p_opts* opts,
+                           void* stream, p2p_plan* out);
+
+/* Plan statistics (paper section 3.2: t, the largest box occupancy; section 3.4.1:
+ * D, the mean number of points per box).  n_pairs and n_zero_pairs are counted on
+ * the device the first time they are asked for (synchronously). */
+p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out);
+
+/* Copies the plan's tables to host memory (any pointer may be NULL):
+ * box_key u64[B], box_start i32[B+1], perm i32[n] (sorted position -> original
+ * index), nbr_start i32[B+1], nbr_idx i32[n_nbr].  Synchronous. */
+p2p_status p2p_plan_export(p2p_plan plan, uint64_t* box_key, int32_t* box_start, int32_t* perm, int32_t* nbr_start,
+                           int32_t* nbr_idx);
+
+/* y = A_near q for nrhs right-hand sides.  dtype must equal the plan's precision;
+ * 1 <= nrhs <= max_rhs.  y is overwritten.  Asynchronous on stream. */
+p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dtype dtype, void* stream);
+
+/* Reverse pass for a real loss L(y), given grad_y = dL/dRe y + i dL/dIm y:
+ *   grad_q = conj(A conj(grad_y))      (A is complex symmetric),
+ *   grad_xyz[i] = sum_j sum_c Re( G'(r_ij) (conj(gy_ic) q_jc + conj(gy_jc) q_ic) ) (x_i - x_j) / r_ij,
+ *   G'(r) = exp(i k r) (i k r - 1) / (4 pi r^2),
+ * with the ids (and so the pair set) held fixed.  grad_q or grad_xyz may be NULL.
+ * grad_xyz is float64 [n,3].  Asynchronous on stream. */
+p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, void* grad_q, double* grad_xyz,
+                              int32_t nrhs, p2p_dtype dtype, void* stream);
+
+/* Frees the plan.  Synchronises the device first, so work already enqueued with
+ * the plan finishes before its memory is released.  NULL is a no-op. */
+p2p_status p2p_plan_destroy(p2p_plan plan);
+
+const char* p2p_status_str(p2p_status s);
+const char* p2p_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2P_H */

@@ -1,0 +1,216 @@
+"""MI355X near-field P2P operator: Python binding of libp2p (include/p2p.h).
+
+Argument marshalling only: every step of the plan build, the apply and the
+reverse pass runs in the HIP library; PyTorch provides device memory and the
+stream.  If the library is not built, importing works but the first call raises
+(there is no other path to the result).
+
+    plan = Plan(xyz, ids, k, dtype=torch.complex64, layout="tiles")
+    y = plan.apply(q)                       # y = A_near q
+    dq, dx = plan.backward(q, grad_y)
+    y = P2PFunction.apply(xyz, q, plan)     # differentiable in q and xyz
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp2p.so")
+
+P2P_C64, P2P_C128 = 1, 2
+LAYOUTS = {"tiles": 0, "csr": 1}
+_STATUS = {0: "ok", 1: "invalid argument", 2: "value out of range", 3: "dtype does not match the plan",
+           4: "out of device memory", 5: "HIP runtime error", 6: "invalid plan"}
+
+
+class P2PError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, message))
+        self.status = status
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("layout", ctypes.c_int), ("max_rhs", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int64), ("n_nbr", ctypes.c_int64),
+                ("n_slots", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_zero_pairs", ctypes.c_int64),
+                ("tile_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("t_max", ctypes.c_int32),
+                ("quantum_exp", ctypes.c_int32), ("d_mean", ctypes.c_double), ("max_sep", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libp2p; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libp2p.so is not built (python -m paper_2403_01596_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.p2p_box_ids.argtypes = [P, i64, P, f64, P, P]
+    L.p2p_plan_create.argtypes = [P, P, i64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
+    L.p2p_plan_info.argtypes = [P, ctypes.POINTER(_Info)]
+    L.p2p_plan_export.argtypes = [P, P, P, P, P, P]
+    L.p2p_apply.argtypes = [P, P, P, i32, ctypes.c_int, P]
+    L.p2p_apply_backward.argtypes = [P, P, P, P, P, i32, ctypes.c_int, P]
+    L.p2p_plan_destroy.argtypes = [P]
+    L.p2p_last_error.restype = ctypes.c_char_p
+    L.p2p_status_str.restype = ctypes.c_char_p
+    L.p2p_status_str.argtypes = [ctypes.c_int]
+    for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
+                 "p2p_apply_backward", "p2p_plan_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise P2PError(rc, lib().p2p_last_error().decode(errors="replace"))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _cuda(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return t.contiguous()
+
+
+def box_ids(xyz: torch.Tensor, origin, h: float) -> torch.Tensor:
+    """floor((xyz - origin) / h) per axis, int32 [n, 3], computed on the device."""
+    xyz = _cuda(xyz, torch.float64, "xyz")
+    n = xyz.shape[0]
+    ids = torch.empty((n, 3), dtype=torch.int32, device=xyz.device)
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    _check(lib().p2p_box_ids(_ptr(xyz), n, o, float(h), _ptr(ids), _stream()))
+    return ids
+
+
+class Plan:
+    """Near-field plan of one point set: boxes, neighbour lists and source lists on the device."""
+
+    def __init__(self, xyz: torch.Tensor, ids: torch.Tensor, k: float, dtype=torch.complex64, layout: str = "tiles",
+                 max_rhs: int = 1):
+        if dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("dtype must be complex64 or complex128")
+        xyz = _cuda(xyz, torch.float64, "xyz")
+        ids = _cuda(ids, torch.int32, "ids")
+        if xyz.dim() != 2 or xyz.shape[1] != 3 or ids.shape != xyz.shape:
+            raise ValueError("xyz and ids must both be [n, 3]")
+        self.dtype = dtype
+        self.layout = layout
+        self.k = float(k)
+        self.n = xyz.shape[0]
+        self.max_rhs = int(max_rhs)
+        self.device = xyz.device
+        opts = _Opts(P2P_C64 if dtype == torch.complex64 else P2P_C128, LAYOUTS[layout], self.max_rhs, 0)
+        h = ctypes.c_void_p()
+        _check(lib().p2p_plan_create(_ptr(xyz), _ptr(ids), self.n, self.k, ctypes.byref(opts), _stream(),
+                                     ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise P2PError(6, "plan has been closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.p2p_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().p2p_plan_info(self.handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _Info._fields_}
+
+    def export(self) -> dict:
+        import numpy as np
+        inf = self.info()
+        B, n = inf["n_boxes"], inf["n_points"]
+        out = dict(box_key=np.empty(B, np.uint64), box_start=np.empty(B + 1, np.int32), perm=np.empty(n, np.int32),
+                   nbr_start=np.empty(B + 1, np.int32), nbr_idx=np.empty(inf["n_nbr"], np.int32))
+        p = lambda a: ctypes.c_void_p(a.ctypes.data)
+        _check(lib().p2p_plan_export(self.handle, p(out["box_key"]), p(out["box_start"]), p(out["perm"]),
+                                     p(out["nbr_start"]), p(out["nbr_idx"])))
+        return out
+
+    def _rhs(self, q: torch.Tensor, name="q"):
+        q = _cuda(q, self.dtype, name)
+        if q.shape[0] != self.n or q.dim() not in (1, 2):
+            raise ValueError("%s must be [n] or [n, m]" % name)
+        return q
+
+    def apply(self, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        q = self._rhs(q)
+        m = 1 if q.dim() == 1 else q.shape[1]
+        y = torch.empty_like(q) if out is None else out
+        if y.shape != q.shape or y.dtype != q.dtype or not y.is_contiguous():
+            raise ValueError("out must be a contiguous tensor shaped like q")
+        dt = P2P_C64 if self.dtype == torch.complex64 else P2P_C128
+        _check(lib().p2p_apply(self.handle, _ptr(q), _ptr(y), m, dt, _stream()))
+        return y
+
+    def backward(self, q: torch.Tensor, grad_y: torch.Tensor, want_dq: bool = True, want_dx: bool = True):
+        q = self._rhs(q)
+        gy = self._rhs(grad_y, "grad_y")
+        if gy.shape != q.shape:
+            raise ValueError("grad_y must be shaped like q")
+        m = 1 if q.dim() == 1 else q.shape[1]
+        dq = torch.empty_like(q) if want_dq else None
+        dx = torch.empty((self.n, 3), dtype=torch.float64, device=q.device) if want_dx else None
+        dt = P2P_C64 if self.dtype == torch.complex64 else P2P_C128
+        _check(lib().p2p_apply_backward(self.handle, _ptr(q), _ptr(gy), _ptr(dq), _ptr(dx), m, dt, _stream()))
+        return dq, dx
+
+
+def apply(plan: Plan, q: torch.Tensor) -> torch.Tensor:
+    return plan.apply(q)
+
+
+class P2PFunction(torch.autograd.Function):
+    """y = A_near(xyz) q, differentiable in q and in the positions.
+
+    The plan fixes the near-field pair set (the ids) and holds the positions it was
+    built from; xyz must be that tensor.  Gradients follow the real-loss convention
+    grad = dL/dRe + i dL/dIm.
+    """
+
+    @staticmethod
+    def forward(ctx, xyz: torch.Tensor, q: torch.Tensor, plan: Plan):
+        ctx.plan = plan
+        ctx.save_for_backward(q)
+        return plan.apply(q)
+
+    @staticmethod
+    def backward(ctx, grad_y: torch.Tensor):
+        (q,) = ctx.saved_tensors
+        want_dx, want_dq = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dq, dx = ctx.plan.backward(q, grad_y.contiguous(), want_dq=want_dq, want_dx=want_dx)
+        return dx, dq, None

@@ -1,0 +1,199 @@
+// C ABI entry points of libp2p: argument validation, plan lifetime, dispatch.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace p2p {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+p2p_status fail(p2p_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+p2p_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? P2P_ERR_NOMEM : P2P_ERR_HIP;
+}
+
+// Keep freed plan memory in the device's stream-ordered pool so that building a
+// plan again does not go back to the driver.
+static p2p_status prepare_pool(int dev) {
+  static std::mutex mu;
+  static bool done[64] = {};
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0 || dev >= 64 || done[dev]) return P2P_OK;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = ~0ull;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+  done[dev] = true;
+  return P2P_OK;
+}
+
+static p2p_status check_plan(p2p_plan_s* P) {
+  if (!P || P->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle");
+  return P2P_OK;
+}
+
+static p2p_status free_plan(p2p_plan_s* P) {
+  p2p_status rc = P2P_OK;
+  if (hipDeviceSynchronize() != hipSuccess) rc = fail(P2P_ERR_HIP, "hipDeviceSynchronize failed in destroy");
+  if (P->arena) (void)hipFreeAsync(P->arena, nullptr);
+  if (P->arena2) (void)hipFreeAsync(P->arena2, nullptr);
+  (void)hipStreamSynchronize(nullptr);
+  P->magic = 0;
+  delete P;
+  return rc;
+}
+
+}  // namespace p2p
+
+using namespace p2p;
+
+extern "C" {
+
+const char* p2p_status_str(p2p_status s) {
+  switch (s) {
+    case P2P_OK: return "ok";
+    case P2P_ERR_ARG: return "invalid argument";
+    case P2P_ERR_RANGE: return "value out of range";
+    case P2P_ERR_DTYPE: return "dtype does not match the plan";
+    case P2P_ERR_NOMEM: return "out of device memory";
+    case P2P_ERR_HIP: return "HIP runtime error";
+    case P2P_ERR_STATE: return "invalid plan";
+  }
+  return "unknown status";
+}
+
+const char* p2p_last_error(void) { return g_last_error.c_str(); }
+
+p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
+                       void* stream) {
+  if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
+  if (!origin) return fail(P2P_ERR_ARG, "origin is NULL");
+  if (n > 0 && (!xyz || !box_ijk)) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(P2P_ERR_RANGE, "h must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(P2P_ERR_RANGE, "origin must be finite");
+  return box_ids(xyz, n, origin, h, box_ijk, (hipStream_t)stream);
+}
+
+p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n, double k, const p2p_opts* opts,
+                           void* stream, p2p_plan* out) {
+  if (!out) return fail(P2P_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
+  if (n > 0 && (!xyz || !box_ijk)) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
+  // neighbour-list entries (at most 27 n) are 32-bit offsets
+  if (n > (int64_t)(0x7fffffff / 27)) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
+  if (!std::isfinite(k) || k < 0) return fail(P2P_ERR_RANGE, "k must be finite and >= 0");
+  p2p_opts o{P2P_C64, P2P_LAYOUT_TILES, 1, 0u};
+  if (opts) o = *opts;
+  if (o.precision != P2P_C64 && o.precision != P2P_C128) return fail(P2P_ERR_ARG, "unknown precision");
+  if (o.layout != P2P_LAYOUT_TILES && o.layout != P2P_LAYOUT_CSR) return fail(P2P_ERR_ARG, "unknown layout");
+  if (o.max_rhs < 1 || o.max_rhs > 4096) return fail(P2P_ERR_ARG, "max_rhs must be in [1, 4096]");
+  if (o.flags != 0u) return fail(P2P_ERR_ARG, "flags must be 0");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(P2P_ERR_HIP, "no HIP device");
+  prepare_pool(dev);
+  p2p_plan_s* P = new (std::nothrow) p2p_plan_s();
+  if (!P) return fail(P2P_ERR_NOMEM, "host allocation failed");
+  std::memset(P, 0, sizeof(*P));
+  P->magic = kPlanMagic;
+  P->device = dev;
+  P->n = n;
+  P->k = k;
+  P->precision = o.precision;
+  P->layout = o.layout;
+  P->max_rhs = o.max_rhs;
+  P->n_pairs = -1;
+  P->n_zero = -1;
+  p2p_status rc = build_plan(P, xyz, box_ijk, (hipStream_t)stream);
+  if (rc != P2P_OK) {
+    std::string msg = g_last_error;
+    free_plan(P);
+    set_error(msg);
+    return rc;
+  }
+  *out = P;
+  return P2P_OK;
+}
+
+p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  if (!out) return fail(P2P_ERR_ARG, "out is NULL");
+  rc = count_pairs(plan, nullptr);
+  if (rc != P2P_OK) return rc;
+  out->n_points = plan->n;
+  out->n_boxes = plan->B;
+  out->n_nbr = plan->nnz;
+  out->n_slots = plan->n_slots;
+  out->n_pairs = plan->n_pairs;
+  out->n_zero_pairs = plan->n_zero;
+  out->tile_entries = plan->tile_len;
+  out->device_bytes = (int64_t)plan->device_bytes;
+  out->t_max = plan->t_max;
+  out->quantum_exp = plan->precision == P2P_C64 ? plan->qexp : 0;
+  out->d_mean = plan->B ? (double)plan->n / (double)plan->B : 0.0;
+  out->max_sep = plan->max_sep;
+  return P2P_OK;
+}
+
+p2p_status p2p_plan_export(p2p_plan plan, uint64_t* box_key, int32_t* box_start, int32_t* perm, int32_t* nbr_start,
+                           int32_t* nbr_idx) {
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  const int64_t B = plan->B, n = plan->n;
+  P2P_HIP(hipDeviceSynchronize());
+  if (box_key && B) P2P_HIP(hipMemcpy(box_key, plan->box_key, sizeof(uint64_t) * B, hipMemcpyDeviceToHost));
+  if (box_start) P2P_HIP(hipMemcpy(box_start, plan->box_start, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost));
+  if (perm && n) P2P_HIP(hipMemcpy(perm, plan->perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (nbr_start) P2P_HIP(hipMemcpy(nbr_start, plan->nbr_start, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost));
+  if (nbr_idx && plan->nnz)
+    P2P_HIP(hipMemcpy(nbr_idx, plan->nbr_idx, sizeof(int32_t) * plan->nnz, hipMemcpyDeviceToHost));
+  return P2P_OK;
+}
+
+static p2p_status check_call(p2p_plan plan, int32_t nrhs, p2p_dtype dtype) {
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  if (dtype != P2P_C64 && dtype != P2P_C128) return fail(P2P_ERR_DTYPE, "unknown dtype");
+  if (dtype != plan->precision) return fail(P2P_ERR_DTYPE, "dtype differs from the plan's precision");
+  if (nrhs < 1 || nrhs > plan->max_rhs) return fail(P2P_ERR_ARG, "nrhs must be in [1, max_rhs]");
+  return P2P_OK;
+}
+
+p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dtype dtype, void* stream) {
+  p2p_status rc = check_call(plan, nrhs, dtype);
+  if (rc != P2P_OK) return rc;
+  if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
+  return launch_apply(plan, q, y, nrhs, (hipStream_t)stream);
+}
+
+p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, void* grad_q, double* grad_xyz,
+                              int32_t nrhs, p2p_dtype dtype, void* stream) {
+  p2p_status rc = check_call(plan, nrhs, dtype);
+  if (rc != P2P_OK) return rc;
+  if (plan->n > 0 && (!q || !grad_y)) return fail(P2P_ERR_ARG, "q or grad_y is NULL");
+  return launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
+}
+
+p2p_status p2p_plan_destroy(p2p_plan plan) {
+  if (!plan) return P2P_OK;
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  return free_plan(plan);
+}
+
+}  // extern "C"

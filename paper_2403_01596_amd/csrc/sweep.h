@@ -1,0 +1,262 @@
+// The near-field sweep shared by the forward and reverse kernels.
+//
+// Paper, sections 3.2 and 3.3: every target loops over the sources of its own and
+// the adjacent boxes and evaluates the pair kernel.  Mapping on CDNA:
+//  - one wavefront per target box (boxes taken from a work list, largest first);
+//  - the 64 lanes hold 64 different sources of the box's neighbourhood, up to
+//    Tr::K chunks of 64 in registers at a time;
+//  - the box's targets are walked one at a time, wave-uniform, with their
+//    coordinates and payload in scalar registers;
+//  - every lane accumulates its sources' terms for the current target, and one
+//    wavefront reduction per target (DPP row operations) yields the target's sum,
+//    which the lane owning that target keeps; outputs are written once, by one
+//    lane, so results do not depend on scheduling and need no atomics.
+// Source layouts:
+//  - TILES: the box's neighbourhood sources replicated into one contiguous list
+//    (the redundant layout of section 3.3, kept per box instead of per target);
+//  - CSR: no replicated geometry; the wavefront writes the sorted positions of
+//    its neighbour boxes' points into LDS (the indexed layout of section 3.2) and
+//    gathers coordinates through them.
+#pragma once
+
+#include <cmath>
+#include <type_traits>
+
+#include "common.h"
+
+namespace p2p {
+
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------------------
+// arithmetic traits
+// ---------------------------------------------------------------------------
+// Pair geometry: given the target and source coordinates, the reciprocal distance
+// (zero when the distance is zero: the pair is skipped), and for the Helmholtz
+// kernel cos and sin of k r and the product k r.
+struct F32 {
+  using coord = int32_t;  // fixed point, units of 2^qexp, low 32 bits
+  using real = float;
+  using cplx = float2;
+  static constexpr int K = 8;
+  struct Geo {
+    float dx, dy, dz, rinv, c, s, kr;
+  };
+  // k_turns: k * 2^qexp / (2 pi), the phase in turns per quantum of distance
+  template <bool HELM>
+  __device__ static __forceinline__ Geo geo(int32_t tx, int32_t ty, int32_t tz, int32_t sx, int32_t sy, int32_t sz,
+                                            float k_turns) {
+    Geo g;
+    // x_target - x_source: exact modulo 2^32, exact as an integer for near pairs
+    g.dx = (float)(int32_t)((uint32_t)tx - (uint32_t)sx);
+    g.dy = (float)(int32_t)((uint32_t)ty - (uint32_t)sy);
+    g.dz = (float)(int32_t)((uint32_t)tz - (uint32_t)sz);
+    const float r2 = __builtin_fmaf(g.dz, g.dz, __builtin_fmaf(g.dy, g.dy, g.dx * g.dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    g.rinv = (r2 > 0.0f) ? ri : 0.0f;
+    if (HELM) {
+      const float turns = (r2 * g.rinv) * k_turns;
+      g.c = __builtin_amdgcn_cosf(turns);
+      g.s = __builtin_amdgcn_sinf(turns);
+      g.kr = turns * 6.28318530717958647692f;
+    } else {
+      g.c = 1.0f;
+      g.s = 0.0f;
+      g.kr = 0.0f;
+    }
+    return g;
+  }
+  __device__ static __forceinline__ float sum(float v) { return wave_sum(v); }
+};
+
+struct F64 {
+  using coord = double;
+  using real = double;
+  using cplx = double2;
+  static constexpr int K = 4;
+  struct Geo {
+    double dx, dy, dz, rinv, c, s, kr;
+  };
+  // k: the wavenumber itself; coordinates are the caller's FP64 values, and the
+  // difference is formed exactly as in the definition, x_target - x_source.
+  template <bool HELM>
+  __device__ static __forceinline__ Geo geo(double tx, double ty, double tz, double sx, double sy, double sz,
+                                            double k) {
+    Geo g;
+    g.dx = tx - sx;
+    g.dy = ty - sy;
+    g.dz = tz - sz;
+    const double r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
+    g.rinv = (r2 > 0.0) ? rsqrt(r2) : 0.0;
+    if (HELM) {
+      g.kr = k * (r2 * g.rinv);
+      sincos(g.kr, &g.s, &g.c);
+    } else {
+      g.c = 1.0;
+      g.s = 0.0;
+      g.kr = 0.0;
+    }
+    return g;
+  }
+  __device__ static __forceinline__ double sum(double v) { return wave_sum(v); }
+};
+
+// ---------------------------------------------------------------------------
+// geometry arguments common to every sweep
+// ---------------------------------------------------------------------------
+template <class Tr>
+struct SweepGeom {
+  const int32_t* work;
+  int32_t nb;
+  const int32_t* box_start;
+  const int32_t* tile_start;
+  const int32_t* tsrc;
+  const typename Tr::coord* tx;  // [3][tl]
+  int64_t tl;
+  const int32_t* nbr_start;
+  const int32_t* nbr_idx;
+  const typename Tr::coord* sx;  // [3][n]
+  int64_t n;
+  const int32_t* perm;
+  typename Tr::real kparam;      // F32: turns per quantum; F64: k
+};
+
+template <class Tr>
+inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
+  SweepGeom<Tr> G;
+  G.work = P->work;
+  G.nb = (int32_t)P->B;
+  G.box_start = P->box_start;
+  G.tile_start = P->tile_start;
+  G.tsrc = P->tile_src;
+  G.tl = P->tile_len;
+  G.nbr_start = P->nbr_start;
+  G.nbr_idx = P->nbr_idx;
+  G.n = P->n;
+  G.perm = P->perm;
+  if constexpr (std::is_same<Tr, F32>::value) {
+    G.tx = P->tile_x32;
+    G.sx = P->sx32;
+    G.kparam = (float)(P->k * std::ldexp(1.0, P->qexp) / (2.0 * M_PI));
+  } else {
+    G.tx = P->tile_x64;
+    G.sx = P->sx64;
+    G.kparam = P->k;
+  }
+  return G;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sorted positions of neighbourhood entries [sg, sg + cap) of box T, into idx.
+__device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, const int32_t* __restrict__ box_start,
+                                            const int32_t* __restrict__ nbr_start,
+                                            const int32_t* __restrict__ nbr_idx, int32_t* idx, int lane) {
+  int32_t off = 0;
+  const int32_t j1 = ld_uniform(nbr_start + T + 1);
+  for (int32_t j = ld_uniform(nbr_start + T); j < j1; ++j) {
+    const int32_t S = ld_uniform(nbr_idx + j);
+    const int32_t a = ld_uniform(box_start + S), len = ld_uniform(box_start + S + 1) - a;
+    const int32_t lo = max(off, sg), hi = min(off + len, sg + cap);
+    for (int32_t e = lo + lane; e < hi; e += kWave) idx[e - sg] = a + (e - off);
+    off += len;
+    if (off >= sg + cap) break;
+  }
+  wave_lds_sync();
+}
+
+// The sweep.  Op supplies:
+//   NP, NT, NA            payload reals per source, per target, accumulators
+//   load_src(p, pay)      payload of the source at sorted position p
+//   load_tgt(t, pay)      payload of the target at sorted position t (uniform)
+//   pair<HELM>(geo, spay, tpay, acc)
+//   store(t, acc)         final values of target t (sorted position), by its lane
+template <class Tr, class Op, bool HELM, bool CSR>
+__device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int32_t* lds) {
+  using real = typename Tr::real;
+  using coord = typename Tr::coord;
+  constexpr int K = Tr::K;
+  constexpr int NP = Op::NP, NT = Op::NT, NA = Op::NA;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t w = uniform((int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
+  if (w >= G.nb) return;
+  const int32_t T = ld_uniform(G.work + w);
+  const int32_t t0 = ld_uniform(G.box_start + T), t1 = ld_uniform(G.box_start + T + 1);
+  int32_t s0 = 0, s1 = 0;
+  if (CSR) {
+    const int32_t j1 = ld_uniform(G.nbr_start + T + 1);
+    for (int32_t j = ld_uniform(G.nbr_start + T); j < j1; ++j) {
+      const int32_t S = ld_uniform(G.nbr_idx + j);
+      s1 += ld_uniform(G.box_start + S + 1) - ld_uniform(G.box_start + S);
+    }
+  } else {
+    s0 = ld_uniform(G.tile_start + T);
+    s1 = ld_uniform(G.tile_start + T + 1);
+  }
+  const int64_t n = G.n, tl = G.tl;
+  for (int32_t tb = t0; tb < t1; tb += kWave) {
+    const int32_t te = min(tb + kWave, t1);
+    real mine[NA];  // lane l: target tb + l
+#pragma unroll
+    for (int a = 0; a < NA; ++a) mine[a] = real(0);
+    for (int32_t sg = s0; sg < s1; sg += kWave * K) {
+      const int nch = min(K, (s1 - sg + kWave - 1) / kWave);
+      if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, lds, lane);
+      coord X[K], Y[K], Z[K];
+      real P[K][NP > 0 ? NP : 1];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        // Entries past the end repeat the group's first source with a zero
+        // payload: a finite term that adds exactly zero.
+        const int32_t e = sg + c * kWave + lane;
+        const bool ok = e < s1;
+        X[c] = Y[c] = Z[c] = coord(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) P[c][a] = real(0);
+        if (c < nch) {
+          int32_t p;
+          if (CSR) {
+            p = lds[ok ? e - sg : 0];
+            X[c] = G.sx[p];
+            Y[c] = G.sx[n + p];
+            Z[c] = G.sx[2 * n + p];
+          } else {
+            const int32_t e2 = ok ? e : sg;
+            p = G.tsrc[e2];
+            X[c] = G.tx[e2];
+            Y[c] = G.tx[tl + e2];
+            Z[c] = G.tx[2 * tl + e2];
+          }
+          if (ok) op.load_src(p, P[c]);
+        }
+      }
+      for (int32_t t = tb; t < te; ++t) {
+        const coord px = ld_uniform(G.sx + t), py = ld_uniform(G.sx + n + t), pz = ld_uniform(G.sx + 2 * n + t);
+        real tp[NT > 0 ? NT : 1];
+        op.load_tgt(t, tp);
+        real acc[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) acc[a] = real(0);
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          if (c < nch) {
+            const typename Tr::Geo g = Tr::template geo<HELM>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+            op.template pair<HELM>(g, P[c], tp, acc);
+          }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const real v = Tr::sum(acc[a]);
+          if (lane == t - tb) mine[a] += v;
+        }
+      }
+      if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
+    }
+    if (tb + lane < te) op.store(tb + lane, mine);
+  }
+}
+
+}  // namespace p2p

@@ -1,0 +1,105 @@
+"""GPU apply y = A_near q against the FP64 oracle.
+
+Bars: relative L2 error <= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path
+(complex64 strengths promoted exactly to complex128 for the oracle).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from cases import plan_cases
+from gpu_helpers import dev, gpu_apply, gpu_plan, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+CASES = list(plan_cases())
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+
+
+def strengths(n, m, dtype, seed=99):
+    q = W.strengths(n, m, np.random.default_rng(seed), np.complex64 if dtype == torch.complex64 else np.complex128)
+    return q
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+def test_apply_matches_oracle(case, dtype, layout):
+    name, xyz, ids, k = case
+    print("apply", name, dtype, layout, flush=True)
+    q = strengths(xyz.shape[0], 1, dtype)
+    y = gpu_apply(gpu_plan(xyz, ids, k, dtype=dtype, layout=layout), q, dtype)
+    yref = oracle.Plan(ids).apply(xyz, k, q)
+    if np.linalg.norm(yref) == 0:
+        assert np.all(y == 0)
+        return
+    err = rel_l2(y, yref)
+    print("  rel L2 %.3e" % err, flush=True)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+def test_multiple_rhs(dtype, layout):
+    inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=11)
+    q = strengths(inst.n, 3, dtype, seed=5)
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=3)
+    y = gpu_apply(P, q, dtype)
+    yref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, q)
+    for c in range(3):
+        assert rel_l2(y[:, c], yref[:, c]) <= TOL[dtype]
+
+
+def test_deterministic_and_layouts_agree():
+    inst = W.ellipsoid(40000, 32, seed=3)
+    q = strengths(inst.n, 1, torch.complex64)
+    Pt = gpu_plan(inst.xyz, inst.ids, inst.k, layout="tiles")
+    Pc = gpu_plan(inst.xyz, inst.ids, inst.k, layout="csr")
+    y1 = gpu_apply(Pt, q, torch.complex64)
+    y2 = gpu_apply(Pt, q, torch.complex64)
+    y3 = gpu_apply(Pc, q, torch.complex64)
+    assert np.array_equal(y1, y2)
+    # the two layouts visit the same sources in the same order
+    assert np.array_equal(y1, y3)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
+def test_invariants_on_gpu_output(dtype):
+    inst = W.sphere(30000, 24, 2 * math.pi * 6, seed=12, dtype=np.complex128)
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype)
+    rng = np.random.default_rng(2)
+    u = strengths(inst.n, 1, dtype, seed=31)
+    v = strengths(inst.n, 1, dtype, seed=32)
+    au = gpu_apply(P, u, dtype)[:, 0]
+    av = gpu_apply(P, v, dtype)[:, 0]
+    lhs = (u[:, 0].astype(np.complex128) * av).sum()
+    rhs = (v[:, 0].astype(np.complex128) * au).sum()
+    # reciprocity: u^T A v = v^T A u
+    assert abs(lhs - rhs) <= 10 * TOL[dtype] * np.sqrt(np.sum(np.abs(u) ** 2) * np.sum(np.abs(av) ** 2))
+    # k = 0: a real operator
+    P0 = gpu_plan(inst.xyz, inst.ids, 0.0, dtype=dtype)
+    yr = gpu_apply(P0, u.real.astype(u.dtype), dtype)
+    assert np.all(yr.imag == 0)
+
+
+def test_sphere_2m_sampled_rows():
+    """The 2M-point sphere at full size, in the benchmark's launch configuration:
+    FP32 and FP64 paths on 4000 sampled rows against the oracle row by row."""
+    inst = W.sphere_2m()
+    print("sphere 2M generated", flush=True)
+    rows = np.random.default_rng(0).choice(inst.n, 4000, replace=False)
+    orc = oracle.Plan(inst.ids)
+    yref = orc.apply_rows(inst.xyz, inst.k, inst.q, rows)
+    for dtype in (torch.complex64, torch.complex128):
+        P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype)
+        y = gpu_apply(P, inst.q, dtype)
+        err = rel_l2(y[rows], yref)
+        print("  %s rel L2 on sampled rows %.3e" % (dtype, err), flush=True)
+        assert err <= TOL[dtype]
+        inf = P.info()
+        assert inf["n_boxes"] > 50000 and inf["t_max"] > 64
+        del P

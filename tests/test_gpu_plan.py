@@ -1,0 +1,89 @@
+"""GPU plan build: box table, permutation and neighbour lists bit-exact with the oracle.
+
+The tables follow the paper's section 3.2 (boxes in Morton order, per-box target
+and neighbour-source index lists with offset arrays), here built on the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_01596_amd as p2p
+import workloads as W
+from cases import plan_cases
+from gpu_helpers import dev, gpu_plan
+
+pytestmark = pytest.mark.gpu
+
+CASES = list(plan_cases())
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+@pytest.mark.parametrize("dtype,layout", [(torch.complex64, "tiles"), (torch.complex128, "csr")])
+def test_tables_bit_exact(case, dtype, layout):
+    name, xyz, ids, k = case
+    print("plan", name, dtype, layout, flush=True)
+    P = gpu_plan(xyz, ids, k, dtype=dtype, layout=layout)
+    got = P.export()
+    ref = oracle.Plan(ids).tables()
+    for key in ("box_key", "box_start", "perm", "nbr_start", "nbr_idx"):
+        assert got[key].dtype == ref[key].dtype, key
+        assert np.array_equal(got[key], ref[key]), key
+    inf = P.info()
+    st = oracle.Plan(ids).stats(xyz)
+    assert inf["n_pairs"] == st["n_pairs"]
+    assert inf["n_zero_pairs"] == st["n_zero_pairs"]
+    assert inf["t_max"] == st["t_max"]
+    assert inf["n_boxes"] == len(ref["box_key"])
+    nb = np.diff(ref["box_start"]).astype(np.int64)
+    per_box = np.array([nb[ref["nbr_idx"][ref["nbr_start"][T]:ref["nbr_start"][T + 1]]].sum()
+                        for T in range(len(nb))], dtype=np.int64)
+    assert inf["n_slots"] == int((nb * per_box).sum())
+    assert inf["tile_entries"] == (int(per_box.sum()) if layout == "tiles" else 0)
+
+
+def test_empty_plan():
+    P = gpu_plan(np.zeros((0, 3)), np.zeros((0, 3), np.int32), 1.0)
+    inf = P.info()
+    assert inf["n_boxes"] == 0 and inf["n_pairs"] == 0
+    y = P.apply(torch.zeros(0, dtype=torch.complex64, device="cuda"))
+    assert y.shape == (0,)
+
+
+def test_box_ids_match_oracle():
+    rng = np.random.default_rng(4)
+    xyz = rng.standard_normal((50000, 3))
+    o = xyz.min(axis=0) - 0.013
+    h = 0.0371
+    got = p2p.box_ids(dev(xyz), o, h).cpu().numpy()
+    assert np.array_equal(got, oracle.box_ids(xyz, o, h))
+    # ties exactly on box faces
+    xyz2 = np.array([[0.5, 0.25, 0.75], [1.0, 0.0, 0.125]])
+    assert np.array_equal(p2p.box_ids(dev(xyz2), (0, 0, 0), 0.125).cpu().numpy(),
+                          oracle.box_ids(xyz2, (0, 0, 0), 0.125))
+
+
+def test_errors_from_device_validation():
+    xyz = np.random.default_rng(0).random((100, 3))
+    ids = W.leaf_ids(xyz, (0, 0, 0), 0.25)
+    bad = ids.copy()
+    bad[17, 1] = 1 << 21
+    with pytest.raises(p2p.P2PError) as e:
+        gpu_plan(xyz, bad, 1.0)
+    assert e.value.status == 2
+    nanx = xyz.copy()
+    nanx[3, 0] = np.nan
+    with pytest.raises(p2p.P2PError) as e:
+        gpu_plan(nanx, ids, 1.0)
+    assert e.value.status == 2
+    with pytest.raises(p2p.P2PError) as e:
+        p2p.box_ids(dev(xyz), (0.5, 0, 0), 0.25)
+    assert e.value.status == 2
+    P = gpu_plan(xyz, ids, 1.0, dtype=torch.complex64)
+    q = torch.ones(100, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(q)
+    rc = p2p.lib().p2p_apply(P.handle, q.data_ptr(), y.data_ptr(), 1, p2p.P2P_C128, None)
+    assert rc == 3  # complex128 strengths on a complex64 plan
+    with pytest.raises(p2p.P2PError) as e:
+        P.apply(torch.ones((100, 2), dtype=torch.complex64, device="cuda"))
+    assert e.value.status == 1
