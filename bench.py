@@ -1,0 +1,251 @@
+"""Benchmark of the near-field P2P operator on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 2M points uniform on the unit sphere, leaf boxes sized for ~32 points
+per non-empty box, k = 2 pi * 64, complex64 strengths ~ N(0,1), one right-hand
+side (seeded, synthetic).  One step is one pass of the whole path on that input,
+already resident in HBM: leaf-box ids from the positions, the plan build (Morton
+keys, sort, box table, neighbour lists, replicated source lists), the FP32 apply
+y = A_near q, and the plan's release.
+
+Printed: one JSON line.  value = near-field interactions (ordered pairs with
+r != 0) per second of the whole step.  Besides it: the apply alone, the FP64 path
+and the non-redundant layout on the same input, the relative L2 error of the
+FP32 and FP64 results against the FP64 oracle, the roofline of the dominant
+kernel (the FP32 sweep) and the oracle's own rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per pair of the FP32 Helmholtz sweep: 3 coordinate differences,
+# 3 operations for r^2, r = r^2 / r, the phase in turns and its range reduction
+# (2), G = (cos, sin) / r (2) and the complex multiply-add (4): 15 VALU operations,
+# plus the transcendentals rsq, sin and cos.  Measured issue rates on the MI355X:
+# 64 lanes per clock per CU for FP32 VALU operations, 32 for transcendentals, so a
+# transcendental takes two issue slots: 21 slots per pair.
+SLOTS_PER_PAIR = 15 + 2 * 3
+CUS, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9
+PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
+PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_tiles_sphere2M_counters.md")
+KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
+                  "paper_2403_01596_amd/csrc/common.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_digest():
+        return None
+    return float(b.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only build the FP32 plan and run the apply --apply-reps times (for counter runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the operator is built and measured on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2403_01596_amd as p2p
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x %d bytes" % (a.numel() * 4))
+        return 0
+
+    inst = W.sphere_2m()
+    log("workload %s: n=%d h=%.6g D=%.2f k=%.4f" % (inst.name, inst.n, inst.h, inst.d_mean, inst.k))
+    xyz = torch.from_numpy(inst.xyz).to(dev)
+    q32 = torch.from_numpy(inst.q[:, 0].copy()).to(dev)
+    q64 = q32.to(torch.complex128)
+    origin = [float(v) for v in inst.origin]
+
+    if args.sweep_only:
+        ids = p2p.box_ids(xyz, origin, inst.h)
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+        for _ in range(args.apply_reps):
+            plan.apply(q32)
+        torch.cuda.synchronize()
+        log("sweep-only: %d applies, %d pairs each" % (args.apply_reps, plan.info()["n_pairs"]))
+        plan.close()
+        return 0
+
+    def step():
+        ids = p2p.box_ids(xyz, origin, inst.h)
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+        y = plan.apply(q32)
+        plan.close()
+        return y
+
+    # ---- the step: box ids + plan + FP32 apply + release
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y32 = step()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    log("step %.3f ms" % (step_s * 1e3))
+
+    # ---- pieces of the step, on resident plans
+    ids = p2p.box_ids(xyz, origin, inst.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan32 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+    plan_s = time.perf_counter() - t0
+    info = plan32.info()
+    n_pairs = info["n_pairs"]
+
+    def time_apply(plan, q, reps):
+        plan.timing(True)
+        plan.apply(q)
+        torch.cuda.synchronize()
+        plan.timing_read()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = plan.apply(q)
+        e1.record()
+        torch.cuda.synchronize()
+        sweep_ms, calls = plan.timing_read()
+        plan.timing(False)
+        return out, e0.elapsed_time(e1) / reps, sweep_ms / calls
+
+    y32, apply32_ms, sweep32_ms = time_apply(plan32, q32, args.apply_reps)
+    log("f32 tiles: apply %.3f ms, sweep kernel %.3f ms" % (apply32_ms, sweep32_ms))
+    plan_csr = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="csr")
+    _, apply_csr_ms, sweep_csr_ms = time_apply(plan_csr, q32, max(3, args.apply_reps // 4))
+    plan_csr.close()
+    log("f32 csr: apply %.3f ms, sweep kernel %.3f ms" % (apply_csr_ms, sweep_csr_ms))
+    plan64 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex128, layout="tiles")
+    y64, apply64_ms, sweep64_ms = time_apply(plan64, q64, max(3, args.apply_reps // 4))
+    plan64.close()
+    log("f64 tiles: apply %.3f ms, sweep kernel %.3f ms" % (apply64_ms, sweep64_ms))
+
+    achieved = n_pairs / (sweep32_ms * 1e-3) / 1e9
+    traffic = stored_traffic()
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_GPAIRS, 1), "unit": "Gpair/s",
+                "frac": round(achieved / PEAK_GPAIRS, 4), "traffic": traffic,
+                "kernel": "sweep FP32 tiles (k_apply<F32,helmholtz,tiles>)",
+                "work_per_pair": "15 VALU + 3 transcendental = %d issue slots" % SLOTS_PER_PAIR,
+                "pairs_per_launch": n_pairs, "kernel_ms": round(sweep32_ms, 4)}
+
+    # ---- oracle on the host cores: every second target row of the same input
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        import oracle
+        orc = oracle.Plan(inst.ids)
+        tb = orc.tables()
+        rows = np.arange(0, inst.n, 2)
+        sizes = np.diff(tb["box_start"]).astype(np.int64)
+        nbr_src = np.array([sizes[tb["nbr_idx"][tb["nbr_start"][T]:tb["nbr_start"][T + 1]]].sum()
+                            for T in range(len(sizes))], dtype=np.int64)
+        pos = np.empty(inst.n, np.int64)
+        pos[tb["perm"]] = np.arange(inst.n)
+        box_of_row = np.searchsorted(tb["box_start"], pos[rows], side="right") - 1
+        # the points are distinct, so each row skips exactly its self pair
+        assert np.unique(inst.xyz, axis=0).shape[0] == inst.n
+        pairs_sample = int(nbr_src[box_of_row].sum() - rows.size)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        t0 = time.perf_counter()
+        yref = orc.apply_rows(inst.xyz, inst.k, inst.q, rows, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(pairs_sample / cpu_s / 1e9, 5), "unit": "Gpair/s", "cores": threads,
+               "kind": "oracle", "seconds": round(cpu_s, 2),
+               "sample": "every second target row of the same 2M-point input (%d rows, %d pairs), "
+                         "FP64, OpenMP over rows" % (rows.size, pairs_sample)}
+        y32h = y32.cpu().numpy()[rows]
+        y64h = y64.cpu().numpy()[rows]
+        ref = yref[:, 0]
+        errs = {"f32": float(np.linalg.norm(y32h - ref) / np.linalg.norm(ref)),
+                "f64": float(np.linalg.norm(y64h - ref) / np.linalg.norm(ref))}
+        log("oracle %.1f s on %d threads; rel L2 f32 %.3e f64 %.3e" % (cpu_s, threads, errs["f32"], errs["f64"]))
+    plan32.close()
+
+    value = n_pairs / step_s / 1e9
+    line = {
+        "metric": "near-field interactions/s (G-pairs/s) at stated rel-err; % of VALU/HBM roofline",
+        "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": inst.name, "n_points": inst.n, "k": inst.k, "leaf_h": inst.h,
+                   "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": "tiles",
+                   "step": "box ids + plan build + FP32 apply + release"},
+        "rel_err": errs or None,
+        "n_pairs": n_pairs,
+        "apply": {"f32_tiles_gpairs_s": round(n_pairs / apply32_ms / 1e6, 2),
+                  "f32_csr_gpairs_s": round(n_pairs / apply_csr_ms / 1e6, 2),
+                  "f64_tiles_gpairs_s": round(n_pairs / apply64_ms / 1e6, 2),
+                  "f32_tiles_ms": round(apply32_ms, 4), "f32_csr_ms": round(apply_csr_ms, 4),
+                  "f64_tiles_ms": round(apply64_ms, 4),
+                  "sweep_ms": {"f32_tiles": round(sweep32_ms, 4), "f32_csr": round(sweep_csr_ms, 4),
+                               "f64_tiles": round(sweep64_ms, 4)}},
+        "plan_ms": round(plan_s * 1e3, 3),
+        "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "tile_entries": info["tile_entries"],
+                 "device_bytes": info["device_bytes"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

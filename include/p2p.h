@@ -134,6 +134,15 @@ p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dt
 p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, void* grad_q, double* grad_xyz,
                               int32_t nrhs, p2p_dtype dtype, void* stream);
 
+/* Diagnostics.  While enabled, p2p_apply and p2p_apply_backward record a pair of
+ * HIP events on their stream around the near-field sweep kernels (the strength
+ * gathers are outside the pair).  p2p_plan_timing_read waits for the recorded
+ * events, returns the summed sweep time in milliseconds and the number of calls
+ * timed, and clears them.  Event creation allocates host objects, so timing must
+ * be off for calls that are captured into a HIP graph. */
+p2p_status p2p_plan_timing(p2p_plan plan, int enable);
+p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls);
+
 /* Frees the plan.  Synchronises the device first, so work already enqueued with
  * the plan finishes before its memory is released.  NULL is a no-op. */
 p2p_status p2p_plan_destroy(p2p_plan plan);

@@ -64,11 +64,13 @@ def lib():
     L.p2p_apply.argtypes = [P, P, P, i32, ctypes.c_int, P]
     L.p2p_apply_backward.argtypes = [P, P, P, P, P, i32, ctypes.c_int, P]
     L.p2p_plan_destroy.argtypes = [P]
+    L.p2p_plan_timing.argtypes = [P, ctypes.c_int]
+    L.p2p_plan_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
     for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
-                 "p2p_apply_backward", "p2p_plan_destroy"):
+                 "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -160,6 +162,16 @@ class Plan:
         _check(lib().p2p_plan_export(self.handle, p(out["box_key"]), p(out["box_start"]), p(out["perm"]),
                                      p(out["nbr_start"]), p(out["nbr_idx"])))
         return out
+
+    def timing(self, enable: bool = True):
+        """Record HIP events around the sweep kernels of later apply/backward calls."""
+        _check(lib().p2p_plan_timing(self.handle, 1 if enable else 0))
+
+    def timing_read(self):
+        """(summed sweep milliseconds, calls timed) since the last read."""
+        ms, calls = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().p2p_plan_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(calls)))
+        return ms.value, calls.value
 
     def _rhs(self, q: torch.Tensor, name="q"):
         q = _cuda(q, self.dtype, name)

@@ -45,9 +45,38 @@ static p2p_status check_plan(p2p_plan_s* P) {
   return P2P_OK;
 }
 
+SweepTimer::SweepTimer(p2p_plan_s* plan, hipStream_t st) : P(plan), s(st) {}
+
+void SweepTimer::start() {
+  if (!P->timing) return;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    e0 = e1 = nullptr;
+    return;
+  }
+  (void)hipEventRecord(e0, s);
+}
+
+void SweepTimer::stop() {
+  if (!P->timing || !e0) return;
+  (void)hipEventRecord(e1, s);
+  P->timed->emplace_back(e0, e1);
+}
+
+static void drop_events(p2p_plan_s* P) {
+  if (!P->timed) return;
+  for (auto& pr : *P->timed) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  P->timed->clear();
+}
+
 static p2p_status free_plan(p2p_plan_s* P) {
   p2p_status rc = P2P_OK;
   if (hipDeviceSynchronize() != hipSuccess) rc = fail(P2P_ERR_HIP, "hipDeviceSynchronize failed in destroy");
+  drop_events(P);
+  delete P->timed;
   if (P->arena) (void)hipFreeAsync(P->arena, nullptr);
   if (P->arena2) (void)hipFreeAsync(P->arena2, nullptr);
   (void)hipStreamSynchronize(nullptr);
@@ -118,6 +147,11 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
   P->max_rhs = o.max_rhs;
   P->n_pairs = -1;
   P->n_zero = -1;
+  P->timed = new (std::nothrow) std::vector<std::pair<hipEvent_t, hipEvent_t>>();
+  if (!P->timed) {
+    delete P;
+    return fail(P2P_ERR_NOMEM, "host allocation failed");
+  }
   p2p_status rc = build_plan(P, xyz, box_ijk, (hipStream_t)stream);
   if (rc != P2P_OK) {
     std::string msg = g_last_error;
@@ -187,6 +221,30 @@ p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, 
   if (rc != P2P_OK) return rc;
   if (plan->n > 0 && (!q || !grad_y)) return fail(P2P_ERR_ARG, "q or grad_y is NULL");
   return launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
+}
+
+p2p_status p2p_plan_timing(p2p_plan plan, int enable) {
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  plan->timing = enable != 0;
+  return P2P_OK;
+}
+
+p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls) {
+  p2p_status rc = check_plan(plan);
+  if (rc != P2P_OK) return rc;
+  if (!ms || !calls) return fail(P2P_ERR_ARG, "ms or calls is NULL");
+  double total = 0.0;
+  for (auto& pr : *plan->timed) {
+    float t = 0.0f;
+    P2P_HIP(hipEventSynchronize(pr.second));
+    P2P_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+    total += t;
+  }
+  *ms = total;
+  *calls = (int64_t)plan->timed->size();
+  drop_events(plan);
+  return P2P_OK;
 }
 
 p2p_status p2p_plan_destroy(p2p_plan plan) {

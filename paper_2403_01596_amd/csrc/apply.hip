@@ -88,10 +88,13 @@ static p2p_status run_apply(p2p_plan_s* P, const void* q, void* y, int m, hipStr
   auto kern = helm ? (csr ? k_apply<Tr, true, true> : k_apply<Tr, true, false>)
                    : (csr ? k_apply<Tr, false, true> : k_apply<Tr, false, false>);
   const real sc = (real)fwd_scale<Tr>(P);
+  SweepTimer timer(P, s);
+  timer.start();
   for (int c = 0; c < m; ++c) {
     FwdOp<Tr> op{(const cplx*)P->q_sorted, m, c, P->perm, (cplx*)y, sc};
     hipLaunchKernelGGL(kern, dim3(grid_for(G.nb, kWavesPerBlock)), dim3(kBlock), 0, s, G, op);
   }
+  timer.stop();
   P2P_HIP(hipGetLastError());
   return P2P_OK;
 }

@@ -139,9 +139,12 @@ static p2p_status run_backward(p2p_plan_s* P, const void* q, const void* gy, voi
   hipLaunchKernelGGL(k_gather_rows2<cplx>, dim3(grid_for(n * m)), dim3(kBlock), 0, s, (const cplx*)q,
                      (const cplx*)gy, P->perm, n, m, (cplx*)P->q_sorted, (cplx*)P->g_sorted);
   SweepGeom<Tr> G = make_geom<Tr>(P);
+  SweepTimer timer(P, s);
+  timer.start();
   if (gq && gx) launch_cols<Tr, true, true>(P, G, gq, gx, m, s);
   else if (gq) launch_cols<Tr, true, false>(P, G, gq, gx, m, s);
   else if (gx) launch_cols<Tr, false, true>(P, G, gq, gx, m, s);
+  timer.stop();
   P2P_HIP(hipGetLastError());
   return P2P_OK;
 }

@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/p2p.h"
 
@@ -73,6 +75,9 @@ struct p2p_plan_s {
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
   void* g_sorted;      // [n * max_rhs] complex
+  // diagnostics: event pairs around the sweep kernels
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* timed;
 };
 
 namespace p2p {
@@ -83,6 +88,16 @@ constexpr uint64_t kPlanMagic = 0x7032705f706c616eull;
 p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipStream_t s);
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s);
 p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids, hipStream_t s);
+
+// diagnostics (api.hip): events around the sweep kernels of one call
+struct SweepTimer {
+  p2p_plan_s* P;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SweepTimer(p2p_plan_s* plan, hipStream_t st);
+  void start();
+  void stop();
+};
 
 // apply / backward (apply.hip, backward.hip)
 p2p_status launch_apply(p2p_plan_s* P, const void* q, void* y, int nrhs, hipStream_t s);
