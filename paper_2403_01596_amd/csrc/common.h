@@ -52,6 +52,7 @@ struct p2p_plan_s {
   int32_t max_rhs;
   int32_t qexp;      // quantum exponent: FP32 coordinates are integers in units of 2^qexp
   double max_sep;    // largest per-axis difference of a near pair
+  bool may_coincide; // bounding boxes of two distinct neighbour boxes intersect
   double max_turns;  // largest k r / (2 pi) over near pairs (bound)
   size_t device_bytes;
   void* arena;       // first allocation: arrays sized by n

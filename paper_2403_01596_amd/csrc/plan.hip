@@ -22,6 +22,7 @@ namespace p2p {
 // device scan (exclusive prefix sum), three passes: tile sums, scan of the tile
 // sums in one workgroup, tile scans plus offsets.
 // ---------------------------------------------------------------------------
+constexpr int kWavesPerBlockPlan = kBlock / kWave;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -205,41 +206,85 @@ static p2p_status radix_sort(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v
 // ---------------------------------------------------------------------------
 // plan kernels
 // ---------------------------------------------------------------------------
-// status words written by the device and read back by the host
-enum { ST_BAD_ID = 0, ST_BAD_X = 1, ST_ID_OR = 2, ST_TMAX = 3, ST_COUNT = 8 };
+// 32-bit status words written by the device and read back by the host.  Minima
+// are kept as maxima of (2^21 - 1 - v), so every word starts at zero.
+enum {
+  ST_BAD_ID = 0, ST_BAD_X, ST_ID_OR, ST_TMAX, ST_LO_X, ST_LO_Y, ST_LO_Z, ST_HI_X, ST_HI_Y, ST_HI_Z, ST_OVERLAP,
+  ST_COUNT
+};
+// 64-bit scalars: pair slots, list entries, near-pair separation bound and the
+// largest |coordinate| (the last two as the bits of non-negative doubles).
+enum { S64_SLOTS = 0, S64_SRCSUM, S64_MAXSEP, S64_MAXABS, S64_COUNT };
 
-__device__ inline void block_or_max(uint32_t* st, uint32_t bad_id, uint32_t bad_x, uint32_t orv) {
-  __shared__ uint32_t s[3];
-  if (threadIdx.x == 0) s[0] = s[1] = s[2] = 0;
-  __syncthreads();
-  if (bad_id) atomicOr(&s[0], 1u);
-  if (bad_x) atomicOr(&s[1], 1u);
-  if (orv) atomicOr(&s[2], orv);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s[0]) atomicOr(&st[ST_BAD_ID], 1u);
-    if (s[1]) atomicOr(&st[ST_BAD_X], 1u);
-    if (s[2]) atomicOr(&st[ST_ID_OR], s[2]);
+constexpr uint32_t kIdMask = (1u << kIdBits) - 1;
+constexpr int kGridStride = 2048;  // workgroups of the grid-stride kernels
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    T o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
   }
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, kWave);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_add(T v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
 }
 
+// Raises *p to at least v; reads first so that most callers skip the atomic.
+__device__ __forceinline__ void raise_u32(uint32_t* p, uint32_t v) {
+  if (v > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, v);
+}
+__device__ __forceinline__ void raise_u64(uint64_t* p, uint64_t v) {
+  if (v > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax((unsigned long long*)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void or_u32(uint32_t* p, uint32_t v) {
+  if ((v | __atomic_load_n(p, __ATOMIC_RELAXED)) != __atomic_load_n(p, __ATOMIC_RELAXED)) atomicOr(p, v);
+}
+
+// Morton keys, identity values, validation, and the bit width and range of the ids.
 __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ xyz, const int32_t* __restrict__ ids,
                                               int64_t n, uint64_t* __restrict__ key, int32_t* __restrict__ idx,
                                               uint32_t* __restrict__ st) {
   int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  uint32_t bad_id = 0, bad_x = 0, orv = 0;
+  uint32_t bad_id = 0, bad_x = 0, orv = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   if (i < n) {
-    int32_t a = ids[3 * i], b = ids[3 * i + 1], c = ids[3 * i + 2];
+    const int32_t a = ids[3 * i], b = ids[3 * i + 1], c = ids[3 * i + 2];
     const uint32_t lim = 1u << kIdBits;
     bad_id = ((uint32_t)a >= lim) | ((uint32_t)b >= lim) | ((uint32_t)c >= lim);
-    double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
     bad_x = !(isfinite(x) && isfinite(y) && isfinite(z));
-    uint32_t ua = (uint32_t)a & (lim - 1), ub = (uint32_t)b & (lim - 1), uc = (uint32_t)c & (lim - 1);
-    orv = ua | ub | uc;
-    key[i] = morton3(ua, ub, uc);
+    const uint32_t u[3] = {(uint32_t)a & kIdMask, (uint32_t)b & kIdMask, (uint32_t)c & kIdMask};
+    orv = u[0] | u[1] | u[2];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = kIdMask - u[d];
+      hi[d] = u[d];
+    }
+    key[i] = morton3(u[0], u[1], u[2]);
     idx[i] = (int32_t)i;
   }
-  block_or_max(st, bad_id, bad_x, orv);
+  bad_id = wave_or(bad_id);
+  bad_x = wave_or(bad_x);
+  orv = wave_or(orv);
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = wave_max(lo[d]);
+    hi[d] = wave_max(hi[d]);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (bad_id) atomicOr(&st[ST_BAD_ID], 1u);
+    if (bad_x) atomicOr(&st[ST_BAD_X], 1u);
+    or_u32(&st[ST_ID_OR], orv);
+    for (int d = 0; d < 3; ++d) {
+      raise_u32(&st[ST_LO_X + d], lo[d]);
+      raise_u32(&st[ST_HI_X + d], hi[d]);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_box_flags(const uint64_t* __restrict__ key, int64_t n,
@@ -248,84 +293,108 @@ __global__ void __launch_bounds__(kBlock) k_box_flags(const uint64_t* __restrict
   if (p < n) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
 }
 
-// flag holds the exclusive scan of the run-start flags: the box of a run start p is flag[p].
+// Dense cell table over the occupied id range plus a one-cell halo of empty
+// cells, so that the 27 lookups of a box need no range checks.
+struct CellGrid {
+  int32_t* table;  // null: look boxes up by binary search instead
+  int32_t x0, y0, z0;
+  int64_t gx, gy;  // extents including the halo
+  __device__ __forceinline__ int64_t cell(int32_t x, int32_t y, int32_t z) const {
+    return ((int64_t)(z - z0 + 1) * gy + (y - y0 + 1)) * gx + (x - x0 + 1);
+  }
+};
+
+// excl holds the exclusive scan of the run-start flags: the box of a run start p is excl[p].
 __global__ void __launch_bounds__(kBlock) k_box_write(const uint64_t* __restrict__ key, int64_t n,
-                                                   const int32_t* __restrict__ excl, uint64_t* __restrict__ box_key,
-                                                   int32_t* __restrict__ box_start, const int32_t* __restrict__ nbox) {
+                                                   const int32_t* __restrict__ excl, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ ids, uint64_t* __restrict__ box_key,
+                                                   int32_t* __restrict__ box_start, const int32_t* __restrict__ nbox,
+                                                   CellGrid grid) {
   int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  bool start = (p == 0 || key[p] != key[p - 1]);
-  if (start) {
-    int32_t b = excl[p];
+  if (p == 0 || key[p] != key[p - 1]) {
+    const int32_t b = excl[p];
     box_key[b] = key[p];
     box_start[b] = (int32_t)p;
+    if (grid.table) {
+      const int64_t i = perm[p];
+      grid.table[grid.cell(ids[3 * i], ids[3 * i + 1], ids[3 * i + 2])] = b;
+    }
   }
   if (p == n - 1) box_start[*nbox] = (int32_t)n;
 }
 
-// Sorted FP64 coordinates (SoA).
-__global__ void __launch_bounds__(kBlock) k_gather_xyz(const double* __restrict__ xyz, const int32_t* __restrict__ perm,
-                                                    int64_t n, double* __restrict__ sx) {
-  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n) return;
-  int64_t i = perm[p];
-  sx[p] = xyz[3 * i];
-  sx[n + p] = xyz[3 * i + 1];
-  sx[2 * n + p] = xyz[3 * i + 2];
-}
-
-// Per-box bounding box of the points (6 doubles per box) and the largest occupancy.
-__global__ void __launch_bounds__(kBlock) k_box_bbox(const double* __restrict__ sx, int64_t n,
-                                                  const int32_t* __restrict__ box_start,
-                                                  const int32_t* __restrict__ nbox, double* __restrict__ bb,
-                                                  uint32_t* __restrict__ st, uint64_t* __restrict__ maxabs) {
-  int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double m = 0.0;
-  if (T < *nbox) {
-    int32_t p0 = box_start[T], p1 = box_start[T + 1];
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = sx[a * n + p0];
-    for (int32_t p = p0 + 1; p < p1; ++p)
-      for (int a = 0; a < 3; ++a) {
-        double v = sx[a * n + p];
-        lo[a] = fmin(lo[a], v);
-        hi[a] = fmax(hi[a], v);
+// One wavefront per box (grid-stride): sorted FP64 coordinates (SoA), the box's
+// bounding box, the largest occupancy and the largest |coordinate|.
+__global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ xyz, const int32_t* __restrict__ perm,
+                                                  int64_t n, const int32_t* __restrict__ box_start,
+                                                  const int32_t* __restrict__ nbox, double* __restrict__ sx,
+                                                  double* __restrict__ bb, uint32_t* __restrict__ st,
+                                                  uint64_t* __restrict__ s64) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t nb = *nbox;
+  uint32_t tmax = 0;
+  double amax = 0.0;
+  for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
+       T += gridDim.x * kWavesPerBlockPlan) {
+    const int32_t p0 = box_start[T], p1 = box_start[T + 1];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t p = p0 + lane; p < p1; p += kWave) {
+      const int64_t i = perm[p];
+      for (int d = 0; d < 3; ++d) {
+        const double v = xyz[3 * i + d];
+        sx[d * n + p] = v;
+        lo[d] = fmin(lo[d], v);
+        hi[d] = fmax(hi[d], v);
       }
-    for (int a = 0; a < 3; ++a) {
-      bb[6 * T + a] = lo[a];
-      bb[6 * T + 3 + a] = hi[a];
-      m = fmax(m, fmax(fabs(lo[a]), fabs(hi[a])));
     }
-    atomicMax(&st[ST_TMAX], (uint32_t)(p1 - p0));
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = -wave_max(-lo[d]);
+      hi[d] = wave_max(hi[d]);
+      amax = fmax(amax, fmax(fabs(lo[d]), fabs(hi[d])));
+    }
+    if (lane == 0)
+      for (int d = 0; d < 3; ++d) {
+        bb[6 * (int64_t)T + d] = lo[d];
+        bb[6 * (int64_t)T + 3 + d] = hi[d];
+      }
+    tmax = max(tmax, (uint32_t)(p1 - p0));
   }
-  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax((unsigned long long*)maxabs, (unsigned long long)__double_as_longlong(m));
+  if (lane == 0) {
+    raise_u32(&st[ST_TMAX], tmax);
+    raise_u64(&s64[S64_MAXABS], (uint64_t)__double_as_longlong(amax));
+  }
 }
 
 __device__ inline int32_t find_box(const uint64_t* __restrict__ box_key, int32_t nb, uint64_t k) {
   int32_t lo = 0, hi = nb;
   while (lo < hi) {
-    int32_t mid = (lo + hi) >> 1;
+    const int32_t mid = (lo + hi) >> 1;
     if (box_key[mid] < k) lo = mid + 1;
     else hi = mid;
   }
   return (lo < nb && box_key[lo] == k) ? lo : -1;
 }
 
-// Neighbour boxes of box T (itself included), ascending.  Returns the count.
-__device__ inline int neighbours(const uint64_t* __restrict__ box_key, int32_t nb, const int32_t* __restrict__ ids,
-                                 int32_t i0, int32_t out[27]) {
-  int32_t bx = ids[3 * (int64_t)i0], by = ids[3 * (int64_t)i0 + 1], bz = ids[3 * (int64_t)i0 + 2];
+// Neighbour boxes of the box holding point i0 (itself included), ascending.
+__device__ inline int neighbours(const uint64_t* __restrict__ box_key, int32_t nb, const CellGrid& grid,
+                                 const int32_t* __restrict__ ids, int32_t i0, int32_t out[27]) {
+  const int32_t bx = ids[3 * (int64_t)i0], by = ids[3 * (int64_t)i0 + 1], bz = ids[3 * (int64_t)i0 + 2];
   const int32_t lim = 1 << kIdBits;
   int cnt = 0;
+  const int64_t c0 = grid.table ? grid.cell(bx, by, bz) : 0;
   for (int dz = -1; dz <= 1; ++dz)
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
-        int32_t x = bx + dx, y = by + dy, z = bz + dz;
-        if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) continue;
-        int32_t S = find_box(box_key, nb, morton3(x, y, z));
+        int32_t S;
+        if (grid.table) {
+          S = grid.table[c0 + ((int64_t)dz * grid.gy + dy) * grid.gx + dx];
+        } else {
+          const int32_t x = bx + dx, y = by + dy, z = bz + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) continue;
+          S = find_box(box_key, nb, morton3(x, y, z));
+        }
         if (S >= 0) {
-          // insertion into the sorted list
           int j = cnt++;
           while (j > 0 && out[j - 1] > S) {
             out[j] = out[j - 1];
@@ -337,60 +406,70 @@ __device__ inline int neighbours(const uint64_t* __restrict__ box_key, int32_t n
   return cnt;
 }
 
-// Per box: neighbour count, source count of the neighbourhood, pair slots
-// (targets x sources) and the largest per-axis coordinate difference to any
-// neighbour (from the bounding boxes).
+// Per box (grid-stride): neighbour count, the neighbourhood's source count, the
+// pair slots (targets x sources) and the largest per-axis coordinate difference
+// to any neighbour, from the bounding boxes.
 __global__ void __launch_bounds__(kBlock) k_nbr_count(const uint64_t* __restrict__ box_key,
                                                    const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ perm, const int32_t* __restrict__ ids,
                                                    const double* __restrict__ bb, const int32_t* __restrict__ nbox,
-                                                   int32_t* __restrict__ cnt, int32_t* __restrict__ src,
-                                                   uint64_t* __restrict__ slots, uint64_t* __restrict__ srcsum,
-                                                   uint64_t* __restrict__ maxsep) {
-  int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  int32_t nb = *nbox;
+                                                   CellGrid grid, int32_t* __restrict__ cnt, int32_t* __restrict__ src,
+                                                   uint64_t* __restrict__ s64, uint32_t* __restrict__ st) {
+  const int32_t nb = *nbox;
   double msep = 0.0;
-  int64_t sl = 0, ss = 0;
-  if (T < nb) {
-    int32_t nbr[27];
-    int c = neighbours(box_key, nb, ids, perm[box_start[T]], nbr);
-    int64_t ssum = 0;
-    for (int e = 0; e < c; ++e) {
-      int32_t S = nbr[e];
-      ssum += box_start[S + 1] - box_start[S];
-      for (int a = 0; a < 3; ++a) {
-        msep = fmax(msep, bb[6 * S + 3 + a] - bb[6 * T + a]);
-        msep = fmax(msep, bb[6 * T + 3 + a] - bb[6 * S + a]);
+  uint32_t overlap = 0;
+  uint64_t sl = 0, ss = 0;
+  const int32_t stride = gridDim.x * kBlock;
+  const int32_t first = blockIdx.x * kBlock + threadIdx.x;
+  // every lane runs the same number of rounds so that the wave reductions see all lanes
+  const int32_t rounds = (nb + stride - 1) / stride;
+  for (int32_t r = 0; r < rounds; ++r) {
+    const int32_t T = first + r * stride;
+    if (T < nb) {
+      int32_t nbr[27];
+      const int c = neighbours(box_key, nb, grid, ids, perm[box_start[T]], nbr);
+      int64_t ssum = 0;
+      for (int e = 0; e < c; ++e) {
+        const int32_t S = nbr[e];
+        ssum += box_start[S + 1] - box_start[S];
+        bool meet = S != T;
+        for (int a = 0; a < 3; ++a) {
+          const double up = bb[6 * (int64_t)S + 3 + a] - bb[6 * (int64_t)T + a];
+          const double dn = bb[6 * (int64_t)T + 3 + a] - bb[6 * (int64_t)S + a];
+          msep = fmax(msep, fmax(up, dn));
+          meet = meet && up >= 0.0 && dn >= 0.0;
+        }
+        // two boxes whose bounding boxes intersect may hold coincident points
+        overlap |= meet ? 1u : 0u;
       }
+      cnt[T] = c;
+      src[T] = (int32_t)(ssum < 0x7fffffff ? ssum : 0x7fffffff);
+      ss += (uint64_t)ssum;
+      sl += (uint64_t)ssum * (uint64_t)(box_start[T + 1] - box_start[T]);
     }
-    cnt[T] = c;
-    src[T] = (int32_t)(ssum < 0x7fffffff ? ssum : 0x7fffffff);
-    ss = ssum;
-    sl = ssum * (int64_t)(box_start[T + 1] - box_start[T]);
   }
-  // one atomic per wave
-  for (int off = 32; off >= 1; off >>= 1) {
-    sl += __shfl_xor(sl, off, kWave);
-    ss += __shfl_xor(ss, off, kWave);
-    msep = fmax(msep, __shfl_xor(msep, off, kWave));
-  }
+  sl = wave_add(sl);
+  ss = wave_add(ss);
+  msep = wave_max(msep);
+  overlap = wave_or(overlap);
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    atomicAdd((unsigned long long*)slots, (unsigned long long)sl);
-    atomicAdd((unsigned long long*)srcsum, (unsigned long long)ss);
-    atomicMax((unsigned long long*)maxsep, (unsigned long long)__double_as_longlong(msep));
+    if (overlap) atomicOr(&st[ST_OVERLAP], 1u);
+    if (sl) atomicAdd((unsigned long long*)&s64[S64_SLOTS], (unsigned long long)sl);
+    if (ss) atomicAdd((unsigned long long*)&s64[S64_SRCSUM], (unsigned long long)ss);
+    raise_u64(&s64[S64_MAXSEP], (uint64_t)__double_as_longlong(msep));
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_nbr_fill(const uint64_t* __restrict__ box_key,
                                                   const int32_t* __restrict__ box_start,
                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ ids,
-                                                  const int32_t* __restrict__ nbr_start, int32_t nb,
+                                                  const int32_t* __restrict__ nbr_start, int32_t nb, CellGrid grid,
                                                   int32_t* __restrict__ nbr_idx) {
-  int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (T >= nb) return;
   int32_t nbr[27];
-  int c = neighbours(box_key, nb, ids, perm[box_start[T]], nbr);
-  int32_t o = nbr_start[T];
+  const int c = neighbours(box_key, nb, grid, ids, perm[box_start[T]], nbr);
+  const int32_t o = nbr_start[T];
   for (int e = 0; e < c; ++e) nbr_idx[o + e] = nbr[e];
 }
 
@@ -399,14 +478,14 @@ __global__ void __launch_bounds__(kBlock) k_nbr_fill(const uint64_t* __restrict_
 // below 2^31 in magnitude, which the choice of qexp guarantees for near pairs.
 __global__ void __launch_bounds__(kBlock) k_fixed(const double* __restrict__ sx, int64_t n3, int qexp,
                                                int32_t* __restrict__ fx) {
-  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n3) return;
-  double v = rint(ldexp(sx[p], -qexp));
+  const double v = rint(ldexp(sx[p], -qexp));
   fx[p] = (int32_t)(uint32_t)(uint64_t)(int64_t)v;
 }
 
-// Replicated source lists: one wavefront per target box copies the points of every
-// neighbour box, in neighbour order, into the box's contiguous list.
+// Replicated source lists: one wavefront per target box copies the points of its
+// neighbourhood into the box's contiguous list, its own points first.
 template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ nbr_start,
@@ -415,15 +494,17 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
                                                    int64_t tl, const double* __restrict__ sx64,
                                                    const int32_t* __restrict__ sx32, int32_t* __restrict__ tsrc,
                                                    double* __restrict__ t64, int32_t* __restrict__ t32) {
-  int64_t T = uniform((int)((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave));
+  const int32_t T = uniform((int32_t)(blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave));
   if (T >= nb) return;
   const int lane = threadIdx.x & (kWave - 1);
   int64_t o = tile_start[T];
-  for (int32_t e = nbr_start[T]; e < nbr_start[T + 1]; ++e) {
-    int32_t S = nbr_idx[e];
-    int32_t p0 = box_start[S], ns = box_start[S + 1] - p0;
+  // the box's own points first, then the other neighbours in list order
+  for (int32_t e = nbr_start[T] - 1; e < nbr_start[T + 1]; ++e) {
+    const int32_t S = e < nbr_start[T] ? T : nbr_idx[e];
+    if (e >= nbr_start[T] && S == T) continue;
+    const int32_t p0 = box_start[S], ns = box_start[S + 1] - p0;
     for (int32_t j = lane; j < ns; j += kWave) {
-      int64_t p = p0 + j, d = o + j;
+      const int64_t p = p0 + j, d = o + j;
       tsrc[d] = (int32_t)p;
       if (F64) {
         t64[d] = sx64[p];
@@ -439,15 +520,16 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
   }
 }
 
-// Cost key for the processing order: boxes with more pair slots first.
+// Processing order of the sweep: boxes in decreasing order of their pair slots,
+// bucketed on a log scale (8 buckets per octave), Morton order inside a bucket.
 __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ src, int32_t nb,
                                                    uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
-  int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (T >= nb) return;
-  uint64_t c = (uint64_t)(box_start[T + 1] - box_start[T]) * (uint64_t)src[T];
-  if (c > 0xffffffffull) c = 0xffffffffull;
-  key[T] = 0xffffffffull - c;
+  const double c = (double)(box_start[T + 1] - box_start[T]) * (double)src[T];
+  const int b = (int)fmin(255.0, floor(log2(c + 1.0) * 8.0));
+  key[T] = (uint64_t)(255 - b);
   idx[T] = (int32_t)T;
 }
 
@@ -457,30 +539,30 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
                                                     const int32_t* __restrict__ nbr_start,
                                                     const int32_t* __restrict__ nbr_idx, int32_t nb,
                                                     unsigned long long* __restrict__ zero) {
-  int64_t T = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int64_t T = (int64_t)blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long z = 0;
   if (T < nb) {
     for (int32_t t = box_start[T]; t < box_start[T + 1]; ++t) {
-      double x = sx[t], y = sx[n + t], w = sx[2 * n + t];
+      const double x = sx[t], y = sx[n + t], w = sx[2 * n + t];
       for (int32_t e = nbr_start[T]; e < nbr_start[T + 1]; ++e) {
-        int32_t S = nbr_idx[e];
+        const int32_t S = nbr_idx[e];
         for (int32_t p = box_start[S] + lane; p < box_start[S + 1]; p += kWave)
           z += (sx[p] == x && sx[n + p] == y && sx[2 * n + p] == w) ? 1 : 0;
       }
     }
   }
-  for (int off = 32; off >= 1; off >>= 1) z += __shfl_xor(z, off, kWave);
+  z = wave_add(z);
   if (lane == 0 && z) atomicAdd(zero, z);
 }
 
 __global__ void __launch_bounds__(kBlock) k_box_ids(const double* __restrict__ xyz, int64_t n3, double ox, double oy,
                                                  double oz, double h, int32_t* __restrict__ ids,
                                                  uint32_t* __restrict__ bad) {
-  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n3) return;
-  int a = (int)(e % 3);
-  double o = a == 0 ? ox : (a == 1 ? oy : oz);
+  const int a = (int)(e % 3);
+  const double o = a == 0 ? ox : (a == 1 ? oy : oz);
   double v = floor((xyz[e] - o) / h);
   if (!(v >= 0.0 && v < (double)(1 << kIdBits))) {
     atomicOr(bad, 1u);
@@ -534,6 +616,9 @@ int bit_length(uint32_t v) {
   }
   return b;
 }
+
+// Largest dense cell table, in cells: 32 bytes per point or 64 MB, whichever is larger.
+int64_t table_cell_limit(int64_t n) { return std::max<int64_t>(16ll << 20, 8 * n); }
 
 }  // namespace
 
@@ -593,8 +678,8 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   // ---- temporaries, freed before returning
   const int64_t g_rs = grid_for(n, kRsTile);
   const int64_t scan_parts = grid_for(std::max<int64_t>(256 * g_rs, n + 1), kScanTile);
-  uint64_t *k0, *k1, *slots, *srcsum, *maxsep, *maxabs;
-  int32_t *v1, *flag, *cnt, *src, *part32, *tot32;
+  uint64_t *k0, *k1, *s64;
+  int32_t *v1, *flag, *cnt, *src, *part32, *tot;
   uint32_t *hist, *partu, *st;
   double* bb;
   auto carvet = [&](Bump& b) {
@@ -609,11 +694,8 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     part32 = b.take<int32_t>(scan_parts);
     bb = b.take<double>(6 * n);
     st = b.take<uint32_t>(ST_COUNT);
-    tot32 = b.take<int32_t>(4);
-    slots = b.take<uint64_t>(4);
-    srcsum = slots + 1;
-    maxsep = slots + 2;
-    maxabs = slots + 3;
+    s64 = b.take<uint64_t>(S64_COUNT);
+    tot = b.take<int32_t>(2);
   };
   size_t bytest = measure(carvet);
   void* tmp = nullptr;
@@ -625,13 +707,13 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     ~TmpGuard() {
       if (p) (void)hipFreeAsync(p, s);
     }
-  } guard{tmp, s};
+  } guard{tmp, s}, guard_table{nullptr, s};
   {
     Bump b{(char*)tmp, 0, bytest};
     carvet(b);
   }
   P2P_HIP(hipMemsetAsync(st, 0, sizeof(uint32_t) * ST_COUNT, s));
-  P2P_HIP(hipMemsetAsync(slots, 0, sizeof(uint64_t) * 4, s));
+  P2P_HIP(hipMemsetAsync(s64, 0, sizeof(uint64_t) * S64_COUNT, s));
   P2P_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), s));
   P2P_HIP(hipMemsetAsync(src, 0, sizeof(int32_t) * (n + 1), s));
 
@@ -643,6 +725,27 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   P2P_HIP(hipStreamSynchronize(s));
   if (hst[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a box id falls outside [0, 2^21)");
   if (hst[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
+
+  // dense cell table when the occupied id range is small enough
+  CellGrid grid{nullptr, 0, 0, 0, 0, 0};
+  {
+    const int32_t lo[3] = {(int32_t)(kIdMask - hst[ST_LO_X]), (int32_t)(kIdMask - hst[ST_LO_Y]),
+                           (int32_t)(kIdMask - hst[ST_LO_Z])};
+    const int64_t ext[3] = {(int64_t)hst[ST_HI_X] - lo[0] + 3, (int64_t)hst[ST_HI_Y] - lo[1] + 3,
+                            (int64_t)hst[ST_HI_Z] - lo[2] + 3};
+    const double cells = (double)ext[0] * (double)ext[1] * (double)ext[2];
+    if (cells <= (double)table_cell_limit(n)) {
+      void* tp = nullptr;
+      rc = dev_alloc(&tp, sizeof(int32_t) * (size_t)cells, s);
+      if (rc == P2P_OK) {
+        guard_table.p = tp;
+        P2P_HIP(hipMemsetAsync(tp, 0xff, sizeof(int32_t) * (size_t)cells, s));  // -1: no box
+        grid = CellGrid{(int32_t*)tp, lo[0], lo[1], lo[2], ext[0], ext[1]};
+      } else {
+        set_error("");  // no room for the table: fall back to binary search
+      }
+    }
+  }
 
   // ---- 2. stable sort of the points by key, over the key bits in use
   const int bits = 3 * bit_length(hst[ST_ID_OR]);
@@ -657,38 +760,42 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   hipLaunchKernelGGL(k_box_flags, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag);
   rc = scan<int32_t>(flag, flag, n, part32, dnb, s);
   if (rc != P2P_OK) return rc;
-  hipLaunchKernelGGL(k_box_write, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag, P->box_key, P->box_start, dnb);
-  hipLaunchKernelGGL(k_gather_xyz, dim3(grid_for(n)), dim3(kBlock), 0, s, xyz, P->perm, n, P->sx64);
-  hipLaunchKernelGGL(k_box_bbox, dim3(grid_for(n)), dim3(kBlock), 0, s, P->sx64, n, P->box_start, dnb, bb, st, maxabs);
+  hipLaunchKernelGGL(k_box_write, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag, P->perm, ids, P->box_key,
+                     P->box_start, dnb, grid);
+  const unsigned gs = (unsigned)std::min<int64_t>(kGridStride, grid_for(n, kWavesPerBlockPlan));
+  hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, dnb, P->sx64, bb, st,
+                     s64);
 
   // ---- 4. neighbour counts, neighbourhood source counts, separation bound.
   //         Entries past the last box stay zero, so scanning n entries gives the
   //         offsets of the B boxes and, at index B, the totals.
-  hipLaunchKernelGGL(k_nbr_count, dim3(grid_for(n)), dim3(kBlock), 0, s, P->box_key, P->box_start, P->perm, ids, bb,
-                     dnb, cnt, src, slots, srcsum, maxsep);
+  const unsigned gt = (unsigned)std::min<int64_t>(kGridStride, grid_for(n));
+  hipLaunchKernelGGL(k_nbr_count, dim3(gt), dim3(kBlock), 0, s, P->box_key, P->box_start, P->perm, ids, bb, dnb, grid,
+                     cnt, src, s64, st);
   P2P_HIP(hipGetLastError());
-  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, tot32, s);
+  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, tot, s);  // tot[0] = list entries
   if (rc != P2P_OK) return rc;
   rc = scan<int32_t>(src, P->tile_start, n + 1, part32, nullptr, s);
   if (rc != P2P_OK) return rc;
 
   // second readback: sizes of the lists and the geometry bounds
   int32_t hB = 0, hnnz = 0;
-  uint64_t h4[4];
+  uint64_t h64[S64_COUNT];
   P2P_HIP(hipMemcpyAsync(&hB, dnb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipMemcpyAsync(&hnnz, tot32, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipMemcpyAsync(h4, slots, sizeof(h4), hipMemcpyDeviceToHost, s));
+  P2P_HIP(hipMemcpyAsync(&hnnz, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  P2P_HIP(hipMemcpyAsync(h64, s64, sizeof(h64), hipMemcpyDeviceToHost, s));
   P2P_HIP(hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
   P2P_HIP(hipStreamSynchronize(s));
   const int32_t B = hB;
   P->B = B;
   P->nnz = hnnz;
-  P->n_slots = (int64_t)h4[0];
+  P->n_slots = (int64_t)h64[S64_SLOTS];
   P->t_max = (int32_t)hst[ST_TMAX];
-  const int64_t srclen = (int64_t)h4[1];
+  P->may_coincide = hst[ST_OVERLAP] != 0;
+  const int64_t srclen = (int64_t)h64[S64_SRCSUM];
   double sep, xabs;
-  std::memcpy(&sep, &h4[2], sizeof(double));
-  std::memcpy(&xabs, &h4[3], sizeof(double));
+  std::memcpy(&sep, &h64[S64_MAXSEP], sizeof(double));
+  std::memcpy(&xabs, &h64[S64_MAXABS], sizeof(double));
   P->max_sep = sep;
   if (srclen > 0x7fffffffll) return fail(P2P_ERR_RANGE, "the per-box source lists exceed 2^31 entries");
   P->tile_len = tiles ? srclen : 0;
@@ -722,10 +829,10 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     carve2(b);
   }
   hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_key, P->box_start, P->perm, ids,
-                     P->nbr_start, B, P->nbr_idx);
+                     P->nbr_start, B, grid, P->nbr_idx);
   if (!f64) hipLaunchKernelGGL(k_fixed, dim3(grid_for(3 * n)), dim3(kBlock), 0, s, P->sx64, 3 * n, P->qexp, P->sx32);
   if (tiles) {
-    unsigned g = grid_for(B, kBlock / kWave);
+    const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)
       hipLaunchKernelGGL(k_tile_fill<true>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
@@ -733,10 +840,10 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
       hipLaunchKernelGGL(k_tile_fill<false>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
   }
-  // processing order: boxes with the most pair slots first (stable, so ties stay in key order)
+  // processing order: most pair slots first (one 8-bit radix pass, stable)
   hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_start, src, B, k0, P->work);
   P2P_HIP(hipGetLastError());
-  rc = radix_sort(k0, P->work, k1, v1, B, 32, hist, partu, &second, s);
+  rc = radix_sort(k0, P->work, k1, v1, B, 8, hist, partu, &second, s);
   if (rc != P2P_OK) return rc;
   if (second) P2P_HIP(hipMemcpyAsync(P->work, v1, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, s));
   P2P_HIP(hipGetLastError());
@@ -751,7 +858,7 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   if (rc != P2P_OK) return rc;
   P2P_HIP(hipMemsetAsync(z, 0, sizeof(unsigned long long), s));
   if (P->B > 0)
-    hipLaunchKernelGGL(k_count_zero, dim3(grid_for(P->B, kBlock / kWave)), dim3(kBlock), 0, s, P->sx64, P->n,
+    hipLaunchKernelGGL(k_count_zero, dim3(grid_for(P->B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx64, P->n,
                        P->box_start, P->nbr_start, P->nbr_idx, (int32_t)P->B, z);
   unsigned long long hz = 0;
   P2P_HIP(hipGetLastError());

@@ -11,7 +11,7 @@
 //    wavefront reduction per target (DPP row operations) yields the target's sum,
 //    which the lane owning that target keeps; outputs are written once, by one
 //    lane, so results do not depend on scheduling and need no atomics.
-// Source layouts:
+// Source layouts (both list a box's own points first, then its other neighbours):
 //  - TILES: the box's neighbourhood sources replicated into one contiguous list
 //    (the redundant layout of section 3.3, kept per box instead of per target);
 //  - CSR: no replicated geometry; the wavefront writes the sorted positions of
@@ -42,8 +42,9 @@ struct F32 {
   struct Geo {
     float dx, dy, dz, rinv, c, s, kr;
   };
-  // k_turns: k * 2^qexp / (2 pi), the phase in turns per quantum of distance
-  template <bool HELM>
+  // k_turns: k * 2^qexp / (2 pi), the phase in turns per quantum of distance.
+  // MASK: the pair may be at distance zero (then rinv = 0 and the term vanishes).
+  template <bool HELM, bool MASK>
   __device__ static __forceinline__ Geo geo(int32_t tx, int32_t ty, int32_t tz, int32_t sx, int32_t sy, int32_t sz,
                                             float k_turns) {
     Geo g;
@@ -53,7 +54,7 @@ struct F32 {
     g.dz = (float)(int32_t)((uint32_t)tz - (uint32_t)sz);
     const float r2 = __builtin_fmaf(g.dz, g.dz, __builtin_fmaf(g.dy, g.dy, g.dx * g.dx));
     const float ri = __builtin_amdgcn_rsqf(r2);
-    g.rinv = (r2 > 0.0f) ? ri : 0.0f;
+    g.rinv = MASK ? ((r2 > 0.0f) ? ri : 0.0f) : ri;
     if (HELM) {
       const float turns = (r2 * g.rinv) * k_turns;
       g.c = __builtin_amdgcn_cosf(turns);
@@ -79,7 +80,7 @@ struct F64 {
   };
   // k: the wavenumber itself; coordinates are the caller's FP64 values, and the
   // difference is formed exactly as in the definition, x_target - x_source.
-  template <bool HELM>
+  template <bool HELM, bool MASK>
   __device__ static __forceinline__ Geo geo(double tx, double ty, double tz, double sx, double sy, double sz,
                                             double k) {
     Geo g;
@@ -87,7 +88,7 @@ struct F64 {
     g.dy = ty - sy;
     g.dz = tz - sz;
     const double r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
-    g.rinv = (r2 > 0.0) ? rsqrt(r2) : 0.0;
+    g.rinv = (!MASK || r2 > 0.0) ? rsqrt(r2) : 0.0;
     if (HELM) {
       g.kr = k * (r2 * g.rinv);
       sincos(g.kr, &g.s, &g.c);
@@ -119,6 +120,7 @@ struct SweepGeom {
   int64_t n;
   const int32_t* perm;
   typename Tr::real kparam;      // F32: turns per quantum; F64: k
+  bool may_coincide;             // points of distinct boxes may coincide: mask every chunk
 };
 
 template <class Tr>
@@ -134,6 +136,7 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
   G.nbr_idx = P->nbr_idx;
   G.n = P->n;
   G.perm = P->perm;
+  G.may_coincide = P->may_coincide;
   if constexpr (std::is_same<Tr, F32>::value) {
     G.tx = P->tile_x32;
     G.sx = P->sx32;
@@ -152,14 +155,17 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sorted positions of neighbourhood entries [sg, sg + cap) of box T, into idx.
+// Sorted positions of neighbourhood entries [sg, sg + cap) of box T, into idx.  The
+// neighbourhood is ordered as the replicated lists are: the box's own points first,
+// then the other neighbour boxes in list order.
 __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, const int32_t* __restrict__ box_start,
                                             const int32_t* __restrict__ nbr_start,
                                             const int32_t* __restrict__ nbr_idx, int32_t* idx, int lane) {
   int32_t off = 0;
-  const int32_t j1 = ld_uniform(nbr_start + T + 1);
-  for (int32_t j = ld_uniform(nbr_start + T); j < j1; ++j) {
-    const int32_t S = ld_uniform(nbr_idx + j);
+  const int32_t j0 = ld_uniform(nbr_start + T), j1 = ld_uniform(nbr_start + T + 1);
+  for (int32_t j = j0 - 1; j < j1; ++j) {
+    const int32_t S = j < j0 ? T : ld_uniform(nbr_idx + j);
+    if (j >= j0 && S == T) continue;
     const int32_t a = ld_uniform(box_start + S), len = ld_uniform(box_start + S + 1) - a;
     const int32_t lo = max(off, sg), hi = min(off + len, sg + cap);
     for (int32_t e = lo + lane; e < hi; e += kWave) idx[e - sg] = a + (e - off);
@@ -244,8 +250,16 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int3
 #pragma unroll
         for (int c = 0; c < K; ++c)
           if (c < nch) {
-            const typename Tr::Geo g = Tr::template geo<HELM>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
-            op.template pair<HELM>(g, P[c], tp, acc);
+            // Only a chunk holding the box's own points (listed first), the padded
+            // tail chunk, or any chunk when boxes overlap, can meet r = 0.
+            const int32_t rel = sg - s0 + c * kWave;
+            if (G.may_coincide || rel < t1 - t0 || rel + kWave > s1 - s0) {
+              const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+              op.template pair<HELM>(g, P[c], tp, acc);
+            } else {
+              const typename Tr::Geo g = Tr::template geo<HELM, false>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+              op.template pair<HELM>(g, P[c], tp, acc);
+            }
           }
 #pragma unroll
         for (int a = 0; a < NA; ++a) {

@@ -30,6 +30,12 @@ def plan_cases():
     x = rng.random((2500, 3))
     ids = rng.integers(0, 5, size=(2500, 3)).astype(np.int32)
     yield "ids_not_positions", x, ids, 4.0
+    # coincident points whose ids put them in adjacent boxes
+    x = rng.random((2000, 3))
+    ids = W.leaf_ids(x, (0, 0, 0), 0.25)
+    x[1000:1010] = x[0:10]
+    ids[1000:1010] = ids[0:10] + np.array([1, 0, 0], np.int32)
+    yield "coincident_across_boxes", x, ids, 6.0
     x = rng.random((4000, 3)) * 6
     x = x[~np.all((x >= 1) & (x < 5), axis=1)]
     yield "hollow_k0", x, W.leaf_ids(x, (0, 0, 0), 1.0), 0.0
