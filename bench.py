@@ -143,6 +143,25 @@ def main():
     step_s = (time.perf_counter() - t0) / args.steps
     log("step %.3f ms" % (step_s * 1e3))
 
+    # ---- where the step's time goes: each phase bracketed by synchronisations
+    phases = {"box_ids": 0.0, "plan_create": 0.0, "apply": 0.0, "release": 0.0}
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids_b = p2p.box_ids(xyz, origin, inst.h)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pl = p2p.Plan(xyz, ids_b, inst.k, dtype=torch.complex64, layout="tiles")
+        t2 = time.perf_counter()
+        pl.apply(q32)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        pl.close()
+        t4 = time.perf_counter()
+        for key, dt in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+            phases[key] += dt * 1e3 / args.steps
+    log("phases (ms): " + ", ".join("%s %.3f" % kv for kv in phases.items()))
+
     # ---- pieces of the step, on resident plans
     ids = p2p.box_ids(xyz, origin, inst.h)
     torch.cuda.synchronize()
@@ -238,6 +257,7 @@ def main():
                   "sweep_ms": {"f32_tiles": round(sweep32_ms, 4), "f32_csr": round(sweep_csr_ms, 4),
                                "f64_tiles": round(sweep64_ms, 4)}},
         "plan_ms": round(plan_s * 1e3, 3),
+        "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "tile_entries": info["tile_entries"],
                  "device_bytes": info["device_bytes"]},
         "roofline": roofline,

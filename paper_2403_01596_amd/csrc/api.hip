@@ -23,23 +23,6 @@ p2p_status hip_fail(hipError_t e, const char* what) {
   return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? P2P_ERR_NOMEM : P2P_ERR_HIP;
 }
 
-// Keep freed plan memory in the device's stream-ordered pool so that building a
-// plan again does not go back to the driver.
-static p2p_status prepare_pool(int dev) {
-  static std::mutex mu;
-  static bool done[64] = {};
-  std::lock_guard<std::mutex> lk(mu);
-  if (dev < 0 || dev >= 64 || done[dev]) return P2P_OK;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = ~0ull;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  (void)hipGetLastError();
-  done[dev] = true;
-  return P2P_OK;
-}
-
 static p2p_status check_plan(p2p_plan_s* P) {
   if (!P || P->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle");
   return P2P_OK;
@@ -74,12 +57,15 @@ static void drop_events(p2p_plan_s* P) {
 
 static p2p_status free_plan(p2p_plan_s* P) {
   p2p_status rc = P2P_OK;
+  int cur = P->device;
+  (void)hipGetDevice(&cur);
+  if (cur != P->device) (void)hipSetDevice(P->device);
   if (hipDeviceSynchronize() != hipSuccess) rc = fail(P2P_ERR_HIP, "hipDeviceSynchronize failed in destroy");
   drop_events(P);
   delete P->timed;
-  if (P->arena) (void)hipFreeAsync(P->arena, nullptr);
-  if (P->arena2) (void)hipFreeAsync(P->arena2, nullptr);
-  (void)hipStreamSynchronize(nullptr);
+  dmem_free(P->arena);
+  dmem_free(P->arena2);
+  if (cur != P->device) (void)hipSetDevice(cur);
   P->magic = 0;
   delete P;
   return rc;
@@ -134,7 +120,6 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
   if (o.flags != 0u) return fail(P2P_ERR_ARG, "flags must be 0");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(P2P_ERR_HIP, "no HIP device");
-  prepare_pool(dev);
   p2p_plan_s* P = new (std::nothrow) p2p_plan_s();
   if (!P) return fail(P2P_ERR_NOMEM, "host allocation failed");
   std::memset(P, 0, sizeof(*P));

@@ -55,8 +55,8 @@ struct FwdOp {
 
 template <class Tr, bool HELM, bool CSR>
 __global__ void __launch_bounds__(kBlock) k_apply(SweepGeom<Tr> G, FwdOp<Tr> op) {
-  __shared__ int32_t lds[CSR ? kWavesPerBlock : 1][CSR ? kWave * Tr::K : 1];
-  sweep<Tr, FwdOp<Tr>, HELM, CSR>(G, op, lds[CSR ? threadIdx.x / kWave : 0]);
+  __shared__ SweepLds<Tr, FwdOp<Tr>, CSR> lds[kWavesPerBlock];
+  sweep<Tr, FwdOp<Tr>, HELM, CSR>(G, op, lds[threadIdx.x / kWave]);
 }
 
 // rows of q (original order) -> rows of qs (sorted order)

@@ -97,8 +97,8 @@ struct BwdOp {
 
 template <class Tr, bool HELM, bool CSR, bool DQ, bool DX>
 __global__ void __launch_bounds__(kBlock) k_backward(SweepGeom<Tr> G, BwdOp<Tr, DQ, DX> op) {
-  __shared__ int32_t lds[CSR ? kWavesPerBlock : 1][CSR ? kWave * Tr::K : 1];
-  sweep<Tr, BwdOp<Tr, DQ, DX>, HELM, CSR>(G, op, lds[CSR ? threadIdx.x / kWave : 0]);
+  __shared__ SweepLds<Tr, BwdOp<Tr, DQ, DX>, CSR> lds[kWavesPerBlock];
+  sweep<Tr, BwdOp<Tr, DQ, DX>, HELM, CSR>(G, op, lds[threadIdx.x / kWave]);
 }
 
 template <typename C>

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -85,6 +86,15 @@ namespace p2p {
 
 constexpr uint64_t kPlanMagic = 0x7032705f706c616eull;
 
+// device memory cache and pinned staging (memory.hip)
+void* dmem_alloc(size_t bytes);  // current device; nullptr when out of memory
+void dmem_free(void* p);         // the caller guarantees no pending work uses p
+struct StagingLock {
+  void* host = nullptr;  // pinned host buffer, valid while the lock is held
+  std::unique_lock<std::mutex> lock;
+};
+StagingLock staging(size_t bytes);
+
 // plan build (plan.hip)
 p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipStream_t s);
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s);
@@ -122,21 +132,91 @@ __device__ __forceinline__ T ld_uniform(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
-// Sum over the 64 lanes of a wavefront; every lane must be active.  The total
-// ends up in lane 63 and is returned to all lanes.  Row-local butterflies
-// (quad permutes, row shifts), then the row broadcasts 15 and 31.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xe, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xc, true));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, false));
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+// Sum over the 64 lanes of a wavefront, valid in lane 63 only; every lane must be
+// active.  Quad butterflies, then row shifts by 4 and 8 (lane 15 of each row holds
+// the row's sum), then the row broadcasts 15 and 31 (lane 63 gathers the four
+// rows).  Every step reads 0 where its source lane does not exist, and the values
+// the broadcasts leave in rows 0-2 never flow into lane 63, so all masks stay full
+// and each step is a single DPP add.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// Reductions to lane 63 for max / or: out-of-range sources return the lane's own
+// value, so no identity element is needed.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_keep_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_keep_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)rhi << 32) | (uint32_t)rlo);
+}
+__device__ __forceinline__ uint32_t wave_max63(uint32_t v) {
+  v = max(v, dpp_keep_u32<0xb1>(v));
+  v = max(v, dpp_keep_u32<0x4e>(v));
+  v = max(v, dpp_keep_u32<0x114>(v));
+  v = max(v, dpp_keep_u32<0x118>(v));
+  v = max(v, dpp_keep_u32<0x142>(v));
+  v = max(v, dpp_keep_u32<0x143>(v));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_or63(uint32_t v) {
+  v |= dpp_keep_u32<0xb1>(v);
+  v |= dpp_keep_u32<0x4e>(v);
+  v |= dpp_keep_u32<0x114>(v);
+  v |= dpp_keep_u32<0x118>(v);
+  v |= dpp_keep_u32<0x142>(v);
+  v |= dpp_keep_u32<0x143>(v);
+  return v;
+}
+__device__ __forceinline__ double wave_max63(double v) {
+  v = fmax(v, dpp_keep_f64<0xb1>(v));
+  v = fmax(v, dpp_keep_f64<0x4e>(v));
+  v = fmax(v, dpp_keep_f64<0x114>(v));
+  v = fmax(v, dpp_keep_f64<0x118>(v));
+  v = fmax(v, dpp_keep_f64<0x142>(v));
+  v = fmax(v, dpp_keep_f64<0x143>(v));
+  return v;
+}
+// 32-bit integer sum to lane 63 (out-of-range sources read 0).
+__device__ __forceinline__ uint32_t wave_add63(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xf, 0xf, true);
+  return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+__device__ __forceinline__ float wave_sum63(float v) {
+  v += dpp_f32<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f32<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f32<0x114>(v);  // row_shr:4
+  v += dpp_f32<0x118>(v);  // row_shr:8
+  v += dpp_f32<0x142>(v);  // row_bcast:15
+  v += dpp_f32<0x143>(v);  // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ double wave_sum63(double v) {
+  v += dpp_f64<0xb1>(v);
+  v += dpp_f64<0x4e>(v);
+  v += dpp_f64<0x114>(v);
+  v += dpp_f64<0x118>(v);
+  v += dpp_f64<0x142>(v);
+  v += dpp_f64<0x143>(v);
   return v;
 }
 
@@ -152,6 +232,17 @@ __host__ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
 }
 __host__ __device__ __forceinline__ uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t iz) {
   return spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+}
+
+// Inverse of spread3: bits 0, 3, 6, ... of x back into a 21-bit integer.
+__host__ __device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x | (x >> 8)) & 0x001f0000ff0000ffull;
+  x = (x | (x >> 16)) & 0x001f00000000ffffull;
+  x = (x | (x >> 32)) & 0x00000000001fffffull;
+  return (uint32_t)x;
 }
 
 inline unsigned grid_for(int64_t n, int per_block = kBlock) {

@@ -1,0 +1,118 @@
+// Device memory cache and pinned staging for the plan build.
+//
+// Plans are built and released often (one per geometry, and every benchmark
+// step), and the driver's allocation calls cost tens to hundreds of
+// microseconds each.  Blocks released by the library are kept per device and
+// handed out again for requests they fit; readbacks of the plan build's small
+// status block go through one pinned host buffer per device.
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace p2p {
+
+namespace {
+
+constexpr size_t kGranule = size_t(2) << 20;          // 2 MiB
+constexpr size_t kCacheCap = size_t(64) << 30;        // cached bytes kept per device at most
+constexpr int kMaxDevices = 64;
+
+struct DeviceCache {
+  std::multimap<size_t, void*> free_blocks;   // size -> block
+  std::unordered_map<void*, size_t> size_of;  // every block handed out or cached
+  size_t cached = 0;
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  std::mutex staging_mu;
+};
+
+std::mutex g_mu;
+DeviceCache g_dev[kMaxDevices];
+
+int current_device() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices) return -1;
+  return d;
+}
+
+void release_cached(DeviceCache& c) {
+  for (auto& kv : c.free_blocks) {
+    (void)hipFree(kv.second);
+    c.size_of.erase(kv.second);
+  }
+  c.free_blocks.clear();
+  c.cached = 0;
+}
+
+}  // namespace
+
+void* dmem_alloc(size_t bytes) {
+  const int d = current_device();
+  if (d < 0) return nullptr;
+  const size_t want = (std::max<size_t>(bytes, 1) + kGranule - 1) / kGranule * kGranule;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCache& c = g_dev[d];
+  // the smallest cached block that fits and wastes at most half of itself
+  auto it = c.free_blocks.lower_bound(want);
+  if (it != c.free_blocks.end() && it->first <= 2 * want) {
+    void* p = it->second;
+    c.cached -= it->first;
+    c.free_blocks.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    release_cached(c);  // give the cache back to the driver and try once more
+    p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  c.size_of[p] = want;
+  return p;
+}
+
+void dmem_free(void* p) {
+  if (!p) return;
+  const int d = current_device();
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (d < 0) return;
+  DeviceCache& c = g_dev[d];
+  auto it = c.size_of.find(p);
+  if (it == c.size_of.end()) return;
+  if (c.cached + it->second > kCacheCap) {
+    c.size_of.erase(it);
+    (void)hipFree(p);
+    return;
+  }
+  c.free_blocks.emplace(it->second, p);
+  c.cached += it->second;
+}
+
+StagingLock staging(size_t bytes) {
+  StagingLock s;
+  const int d = current_device();
+  if (d < 0) return s;
+  DeviceCache& c = g_dev[d];
+  s.lock = std::unique_lock<std::mutex>(c.staging_mu);
+  if (c.staging_bytes < bytes) {
+    if (c.staging) (void)hipHostFree(c.staging);
+    c.staging = nullptr;
+    c.staging_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    if (hipHostMalloc(&c.staging, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c.staging = nullptr;
+      return s;
+    }
+    c.staging_bytes = want;
+  }
+  s.host = c.staging;
+  return s;
+}
+
+}  // namespace p2p

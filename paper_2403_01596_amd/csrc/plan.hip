@@ -101,9 +101,15 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* __restrict__ in,
 // out[0..n) = exclusive prefix of in; *total = sum (device pointer, may be null).
 // part: workspace of at least grid_for(n, kScanTile) elements.  in == out allowed.
 template <typename T>
+__global__ void k_zero_one(T* p) {
+  if (threadIdx.x == 0) *p = T(0);
+}
+
+template <typename T>
 static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s) {
   if (n <= 0) {
-    if (total) P2P_HIP(hipMemsetAsync(total, 0, sizeof(T), s));
+    if (total) hipLaunchKernelGGL(k_zero_one<T>, dim3(1), dim3(kWave), 0, s, total);
+    P2P_HIP(hipGetLastError());
     return P2P_OK;
   }
   unsigned g = grid_for(n, kScanTile);
@@ -206,90 +212,171 @@ static p2p_status radix_sort(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v
 // ---------------------------------------------------------------------------
 // plan kernels
 // ---------------------------------------------------------------------------
-// 32-bit status words written by the device and read back by the host.  Minima
-// are kept as maxima of (2^21 - 1 - v), so every word starts at zero.
+// Status block written by the device and read back by the host in one copy.
+// Minima of the ids are kept as maxima of (2^21 - 1 - v), so everything starts
+// at zero.
 enum {
   ST_BAD_ID = 0, ST_BAD_X, ST_ID_OR, ST_TMAX, ST_LO_X, ST_LO_Y, ST_LO_Z, ST_HI_X, ST_HI_Y, ST_HI_Z, ST_OVERLAP,
   ST_COUNT
 };
-// 64-bit scalars: pair slots, list entries, near-pair separation bound and the
-// largest |coordinate| (the last two as the bits of non-negative doubles).
-enum { S64_SLOTS = 0, S64_SRCSUM, S64_MAXSEP, S64_MAXABS, S64_COUNT };
+struct DevStatus {
+  uint32_t st[16];
+  int32_t nbox;        // boxes (scan total of the run starts)
+  int32_t nnz;         // neighbour-list entries (scan total)
+  uint64_t slots;      // sum over boxes of targets x neighbourhood sources
+  uint64_t srcsum;     // sum over boxes of neighbourhood sources (list length)
+  uint64_t maxsep;     // bits of the largest per-axis near-pair difference (>= 0)
+  uint64_t maxabs;     // bits of the largest |coordinate|
+  uint64_t zero;       // zero-distance pairs (statistics only)
+};
 
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1;
 constexpr int kGridStride = 2048;  // workgroups of the grid-stride kernels
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    T o = __shfl_xor(v, off, kWave);
-    v = o > v ? o : v;
+// Per-workgroup partial results of the reductions over points and boxes.  Each
+// workgroup of a grid-stride kernel writes its own row (no atomics: on a chip of
+// eight dies, same-address atomics from thousands of wavefronts serialise); one
+// small kernel folds the rows into the status block before each readback.
+struct Partial {
+  uint32_t bad;     // bit 0: id out of range, bit 1: coordinate not finite
+  uint32_t id_or;
+  uint32_t lo[3];   // kIdMask - smallest id per axis
+  uint32_t hi[3];   // largest id per axis
+  uint32_t tmax;
+  uint32_t overlap;
+  uint64_t slots, srcsum;
+  double maxsep, maxabs;
+};
+
+__global__ void __launch_bounds__(kBlock) k_fold(const Partial* __restrict__ part, int rows,
+                                              DevStatus* __restrict__ status) {
+  __shared__ Partial acc[kBlock];
+  Partial a{};
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    const Partial& p = part[r];
+    a.bad |= p.bad;
+    a.id_or |= p.id_or;
+    for (int d = 0; d < 3; ++d) {
+      a.lo[d] = max(a.lo[d], p.lo[d]);
+      a.hi[d] = max(a.hi[d], p.hi[d]);
+    }
+    a.tmax = max(a.tmax, p.tmax);
+    a.overlap |= p.overlap;
+    a.slots += p.slots;
+    a.srcsum += p.srcsum;
+    a.maxsep = fmax(a.maxsep, p.maxsep);
+    a.maxabs = fmax(a.maxabs, p.maxabs);
   }
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, kWave);
-  return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_add(T v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  acc[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial t{};
+    for (int i = 0; i < kBlock; ++i) {
+      const Partial& p = acc[i];
+      t.bad |= p.bad;
+      t.id_or |= p.id_or;
+      for (int d = 0; d < 3; ++d) {
+        t.lo[d] = max(t.lo[d], p.lo[d]);
+        t.hi[d] = max(t.hi[d], p.hi[d]);
+      }
+      t.tmax = max(t.tmax, p.tmax);
+      t.overlap |= p.overlap;
+      t.slots += p.slots;
+      t.srcsum += p.srcsum;
+      t.maxsep = fmax(t.maxsep, p.maxsep);
+      t.maxabs = fmax(t.maxabs, p.maxabs);
+    }
+    status->st[ST_BAD_ID] = t.bad & 1u;
+    status->st[ST_BAD_X] = (t.bad >> 1) & 1u;
+    status->st[ST_ID_OR] = t.id_or;
+    for (int d = 0; d < 3; ++d) {
+      status->st[ST_LO_X + d] = t.lo[d];
+      status->st[ST_HI_X + d] = t.hi[d];
+    }
+    status->st[ST_TMAX] = t.tmax;
+    status->st[ST_OVERLAP] = t.overlap;
+    status->slots = t.slots;
+    status->srcsum = t.srcsum;
+    status->maxsep = (uint64_t)__double_as_longlong(t.maxsep);
+    status->maxabs = (uint64_t)__double_as_longlong(t.maxabs);
+  }
 }
 
-// Raises *p to at least v; reads first so that most callers skip the atomic.
-__device__ __forceinline__ void raise_u32(uint32_t* p, uint32_t v) {
-  if (v > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, v);
-}
-__device__ __forceinline__ void raise_u64(uint64_t* p, uint64_t v) {
-  if (v > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ void or_u32(uint32_t* p, uint32_t v) {
-  if ((v | __atomic_load_n(p, __ATOMIC_RELAXED)) != __atomic_load_n(p, __ATOMIC_RELAXED)) atomicOr(p, v);
+// Lane 63 of every wavefront holds its wavefront's value; the first wavefront of
+// the workgroup combines the four through LDS.
+template <typename T, typename F>
+__device__ __forceinline__ T block_combine63(T v, T* lds, F op) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  if (lane == kWave - 1) lds[wv] = v;
+  __syncthreads();
+  T r = lds[0];
+  for (int w = 1; w < kWavesPerBlockPlan; ++w) r = op(r, lds[w]);
+  __syncthreads();
+  return r;
 }
 
-// Morton keys, identity values, validation, and the bit width and range of the ids.
+// Zeroes `words` 32-bit words at `zero` (status block and partial rows) and two
+// counter arrays of n1 entries, and marks every cell of the dense table empty (-1).
+__global__ void __launch_bounds__(kBlock) k_init(uint32_t* __restrict__ zero, int64_t words, int32_t* __restrict__ cnt,
+                                              int32_t* __restrict__ src, int64_t n1, int32_t* __restrict__ table,
+                                              int64_t cells) {
+  const int64_t end = max(max(n1, cells), words);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < end; i += stride) {
+    if (i < n1) {
+      cnt[i] = 0;
+      src[i] = 0;
+    }
+    if (i < cells) table[i] = -1;
+    if (i < words) zero[i] = 0;
+  }
+}
+
+// Morton keys, identity values, validation, and the bit width and range of the
+// ids (grid-stride; one partial row per workgroup).
 __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ xyz, const int32_t* __restrict__ ids,
                                               int64_t n, uint64_t* __restrict__ key, int32_t* __restrict__ idx,
-                                              uint32_t* __restrict__ st) {
-  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  uint32_t bad_id = 0, bad_x = 0, orv = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  if (i < n) {
+                                              Partial* __restrict__ part) {
+  __shared__ uint32_t lds[kWavesPerBlockPlan];
+  uint32_t bad = 0, orv = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  const uint32_t lim = 1u << kIdBits;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     const int32_t a = ids[3 * i], b = ids[3 * i + 1], c = ids[3 * i + 2];
-    const uint32_t lim = 1u << kIdBits;
-    bad_id = ((uint32_t)a >= lim) | ((uint32_t)b >= lim) | ((uint32_t)c >= lim);
+    const bool bad_id = ((uint32_t)a >= lim) | ((uint32_t)b >= lim) | ((uint32_t)c >= lim);
     const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-    bad_x = !(isfinite(x) && isfinite(y) && isfinite(z));
+    const bool bad_x = !(isfinite(x) && isfinite(y) && isfinite(z));
+    bad |= (bad_id ? 1u : 0u) | (bad_x ? 2u : 0u);
     const uint32_t u[3] = {(uint32_t)a & kIdMask, (uint32_t)b & kIdMask, (uint32_t)c & kIdMask};
-    orv = u[0] | u[1] | u[2];
+    orv |= u[0] | u[1] | u[2];
     for (int d = 0; d < 3; ++d) {
-      lo[d] = kIdMask - u[d];
-      hi[d] = u[d];
+      lo[d] = max(lo[d], kIdMask - u[d]);
+      hi[d] = max(hi[d], u[d]);
     }
     key[i] = morton3(u[0], u[1], u[2]);
     idx[i] = (int32_t)i;
   }
-  bad_id = wave_or(bad_id);
-  bad_x = wave_or(bad_x);
-  orv = wave_or(orv);
+  auto vor = [](uint32_t x, uint32_t y) { return x | y; };
+  auto vmax = [](uint32_t x, uint32_t y) { return x > y ? x : y; };
+  bad = block_combine63(wave_or63(bad), lds, vor);
+  orv = block_combine63(wave_or63(orv), lds, vor);
   for (int d = 0; d < 3; ++d) {
-    lo[d] = wave_max(lo[d]);
-    hi[d] = wave_max(hi[d]);
+    lo[d] = block_combine63(wave_max63(lo[d]), lds, vmax);
+    hi[d] = block_combine63(wave_max63(hi[d]), lds, vmax);
   }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (bad_id) atomicOr(&st[ST_BAD_ID], 1u);
-    if (bad_x) atomicOr(&st[ST_BAD_X], 1u);
-    or_u32(&st[ST_ID_OR], orv);
+  if (threadIdx.x == 0) {
+    Partial& p = part[blockIdx.x];
+    p.bad = bad;
+    p.id_or = orv;
     for (int d = 0; d < 3; ++d) {
-      raise_u32(&st[ST_LO_X + d], lo[d]);
-      raise_u32(&st[ST_HI_X + d], hi[d]);
+      p.lo[d] = lo[d];
+      p.hi[d] = hi[d];
     }
   }
 }
 
 __global__ void __launch_bounds__(kBlock) k_box_flags(const uint64_t* __restrict__ key, int64_t n,
                                                    int32_t* __restrict__ flag) {
-  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p < n) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
 }
 
@@ -306,39 +393,42 @@ struct CellGrid {
 
 // excl holds the exclusive scan of the run-start flags: the box of a run start p is excl[p].
 __global__ void __launch_bounds__(kBlock) k_box_write(const uint64_t* __restrict__ key, int64_t n,
-                                                   const int32_t* __restrict__ excl, const int32_t* __restrict__ perm,
-                                                   const int32_t* __restrict__ ids, uint64_t* __restrict__ box_key,
-                                                   int32_t* __restrict__ box_start, const int32_t* __restrict__ nbox,
-                                                   CellGrid grid) {
-  int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                   const int32_t* __restrict__ excl, uint64_t* __restrict__ box_key,
+                                                   int32_t* __restrict__ box_start,
+                                                   const DevStatus* __restrict__ status, CellGrid grid) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  if (p == 0 || key[p] != key[p - 1]) {
+  const uint64_t k = key[p];
+  if (p == 0 || k != key[p - 1]) {
     const int32_t b = excl[p];
-    box_key[b] = key[p];
+    box_key[b] = k;
     box_start[b] = (int32_t)p;
-    if (grid.table) {
-      const int64_t i = perm[p];
-      grid.table[grid.cell(ids[3 * i], ids[3 * i + 1], ids[3 * i + 2])] = b;
-    }
+    if (grid.table) grid.table[grid.cell(compact3(k), compact3(k >> 1), compact3(k >> 2))] = b;
   }
-  if (p == n - 1) box_start[*nbox] = (int32_t)n;
+  if (p == n - 1) box_start[status->nbox] = (int32_t)n;
 }
 
 // One wavefront per box (grid-stride): sorted FP64 coordinates (SoA), the box's
 // bounding box, the largest occupancy and the largest |coordinate|.
 __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ xyz, const int32_t* __restrict__ perm,
                                                   int64_t n, const int32_t* __restrict__ box_start,
-                                                  const int32_t* __restrict__ nbox, double* __restrict__ sx,
-                                                  double* __restrict__ bb, uint32_t* __restrict__ st,
-                                                  uint64_t* __restrict__ s64) {
+                                                  const DevStatus* __restrict__ status, double* __restrict__ sx,
+                                                  double* __restrict__ bb, Partial* __restrict__ part) {
+  __shared__ double ldsd[kWavesPerBlockPlan];
+  __shared__ uint32_t ldsu[kWavesPerBlockPlan];
   const int lane = threadIdx.x & (kWave - 1);
-  const int32_t nb = *nbox;
+  const int32_t nb = status->nbox;
   uint32_t tmax = 0;
   double amax = 0.0;
   for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
        T += gridDim.x * kWavesPerBlockPlan) {
     const int32_t p0 = box_start[T], p1 = box_start[T + 1];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    // lanes past the box's last point repeat its first point
+    double lo[3], hi[3];
+    {
+      const int64_t i0 = perm[p0];
+      for (int d = 0; d < 3; ++d) lo[d] = hi[d] = xyz[3 * i0 + d];
+    }
     for (int32_t p = p0 + lane; p < p1; p += kWave) {
       const int64_t i = perm[p];
       for (int d = 0; d < 3; ++d) {
@@ -349,20 +439,23 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
       }
     }
     for (int d = 0; d < 3; ++d) {
-      lo[d] = -wave_max(-lo[d]);
-      hi[d] = wave_max(hi[d]);
-      amax = fmax(amax, fmax(fabs(lo[d]), fabs(hi[d])));
+      lo[d] = -wave_max63(-lo[d]);
+      hi[d] = wave_max63(hi[d]);
     }
-    if (lane == 0)
+    if (lane == kWave - 1) {
       for (int d = 0; d < 3; ++d) {
         bb[6 * (int64_t)T + d] = lo[d];
         bb[6 * (int64_t)T + 3 + d] = hi[d];
+        amax = fmax(amax, fmax(fabs(lo[d]), fabs(hi[d])));
       }
-    tmax = max(tmax, (uint32_t)(p1 - p0));
+      tmax = max(tmax, (uint32_t)(p1 - p0));
+    }
   }
-  if (lane == 0) {
-    raise_u32(&st[ST_TMAX], tmax);
-    raise_u64(&s64[S64_MAXABS], (uint64_t)__double_as_longlong(amax));
+  tmax = block_combine63(tmax, ldsu, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
+  amax = block_combine63(amax, ldsd, [](double x, double y) { return fmax(x, y); });
+  if (threadIdx.x == 0) {
+    part[blockIdx.x].tmax = tmax;
+    part[blockIdx.x].maxabs = amax;
   }
 }
 
@@ -376,101 +469,97 @@ __device__ inline int32_t find_box(const uint64_t* __restrict__ box_key, int32_t
   return (lo < nb && box_key[lo] == k) ? lo : -1;
 }
 
-// Neighbour boxes of the box holding point i0 (itself included), ascending.
-__device__ inline int neighbours(const uint64_t* __restrict__ box_key, int32_t nb, const CellGrid& grid,
-                                 const int32_t* __restrict__ ids, int32_t i0, int32_t out[27]) {
-  const int32_t bx = ids[3 * (int64_t)i0], by = ids[3 * (int64_t)i0 + 1], bz = ids[3 * (int64_t)i0 + 2];
+// Lane l < 27 of a wavefront: the neighbour of box T at offset
+// (l % 3 - 1, l / 3 % 3 - 1, l / 9 - 1), or -1 if that box is empty or off the grid.
+__device__ __forceinline__ int32_t neighbour_lane(const uint64_t* __restrict__ box_key, int32_t nb,
+                                                  const CellGrid& grid, uint64_t kT, int lane) {
+  if (lane >= 27) return -1;
+  const int32_t x = (int32_t)compact3(kT) + lane % 3 - 1;
+  const int32_t y = (int32_t)compact3(kT >> 1) + lane / 3 % 3 - 1;
+  const int32_t z = (int32_t)compact3(kT >> 2) + lane / 9 - 1;
+  if (grid.table) return grid.table[grid.cell(x, y, z)];
   const int32_t lim = 1 << kIdBits;
-  int cnt = 0;
-  const int64_t c0 = grid.table ? grid.cell(bx, by, bz) : 0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        int32_t S;
-        if (grid.table) {
-          S = grid.table[c0 + ((int64_t)dz * grid.gy + dy) * grid.gx + dx];
-        } else {
-          const int32_t x = bx + dx, y = by + dy, z = bz + dz;
-          if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) continue;
-          S = find_box(box_key, nb, morton3(x, y, z));
-        }
-        if (S >= 0) {
-          int j = cnt++;
-          while (j > 0 && out[j - 1] > S) {
-            out[j] = out[j - 1];
-            --j;
-          }
-          out[j] = S;
-        }
-      }
-  return cnt;
+  if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+  return find_box(box_key, nb, morton3(x, y, z));
 }
 
-// Per box (grid-stride): neighbour count, the neighbourhood's source count, the
-// pair slots (targets x sources) and the largest per-axis coordinate difference
-// to any neighbour, from the bounding boxes.
-__global__ void __launch_bounds__(kBlock) k_nbr_count(const uint64_t* __restrict__ box_key,
-                                                   const int32_t* __restrict__ box_start,
-                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ ids,
-                                                   const double* __restrict__ bb, const int32_t* __restrict__ nbox,
-                                                   CellGrid grid, int32_t* __restrict__ cnt, int32_t* __restrict__ src,
-                                                   uint64_t* __restrict__ s64, uint32_t* __restrict__ st) {
-  const int32_t nb = *nbox;
+// One wavefront per box (grid-stride), one lane per neighbour offset.  Counting
+// pass: the number of neighbours, the neighbourhood's source count, the pair
+// slots and, from the bounding boxes, the largest per-axis coordinate difference
+// to any neighbour and whether two distinct boxes' bounding boxes intersect.
+// Filling pass: the neighbour indices in ascending order.
+template <bool FILL>
+__global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box_key,
+                                             const int32_t* __restrict__ box_start, const double* __restrict__ bb,
+                                             const DevStatus* __restrict__ status, CellGrid grid,
+                                             int32_t* __restrict__ cnt, int32_t* __restrict__ src,
+                                             const int32_t* __restrict__ nbr_start, int32_t* __restrict__ nbr_idx,
+                                             Partial* __restrict__ part) {
+  __shared__ uint64_t ldsl[kWavesPerBlockPlan];
+  __shared__ double ldsd[kWavesPerBlockPlan];
+  __shared__ uint32_t ldsu[kWavesPerBlockPlan];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t nb = status->nbox;
+  uint64_t slots = 0, srcsum = 0;
   double msep = 0.0;
   uint32_t overlap = 0;
-  uint64_t sl = 0, ss = 0;
-  const int32_t stride = gridDim.x * kBlock;
-  const int32_t first = blockIdx.x * kBlock + threadIdx.x;
-  // every lane runs the same number of rounds so that the wave reductions see all lanes
-  const int32_t rounds = (nb + stride - 1) / stride;
-  for (int32_t r = 0; r < rounds; ++r) {
-    const int32_t T = first + r * stride;
-    if (T < nb) {
-      int32_t nbr[27];
-      const int c = neighbours(box_key, nb, grid, ids, perm[box_start[T]], nbr);
-      int64_t ssum = 0;
-      for (int e = 0; e < c; ++e) {
-        const int32_t S = nbr[e];
-        ssum += box_start[S + 1] - box_start[S];
-        bool meet = S != T;
+  for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
+       T += gridDim.x * kWavesPerBlockPlan) {
+    const uint64_t kT = ld_uniform(box_key + T);
+    const int32_t S = neighbour_lane(box_key, nb, grid, kT, lane);
+    const bool found = S >= 0;
+    if (FILL) {
+      // rank among the found neighbours by box index (= by key)
+      int32_t rank = 0;
+      for (int j = 0; j < 27; ++j) {
+        const int32_t Sj = __builtin_amdgcn_readlane(S, j);
+        rank += (Sj >= 0 && Sj < S) ? 1 : 0;
+      }
+      if (found) nbr_idx[ld_uniform(nbr_start + T) + rank] = S;
+    } else {
+      uint32_t ns = 0;
+      double sep = 0.0;
+      uint32_t meet = 0;
+      if (found) {
+        ns = (uint32_t)(box_start[S + 1] - box_start[S]);
+        bool inter = S != T;
         for (int a = 0; a < 3; ++a) {
           const double up = bb[6 * (int64_t)S + 3 + a] - bb[6 * (int64_t)T + a];
           const double dn = bb[6 * (int64_t)T + 3 + a] - bb[6 * (int64_t)S + a];
-          msep = fmax(msep, fmax(up, dn));
-          meet = meet && up >= 0.0 && dn >= 0.0;
+          sep = fmax(sep, fmax(up, dn));
+          inter = inter && up >= 0.0 && dn >= 0.0;
         }
-        // two boxes whose bounding boxes intersect may hold coincident points
-        overlap |= meet ? 1u : 0u;
+        meet = inter ? 1u : 0u;
       }
-      cnt[T] = c;
-      src[T] = (int32_t)(ssum < 0x7fffffff ? ssum : 0x7fffffff);
-      ss += (uint64_t)ssum;
-      sl += (uint64_t)ssum * (uint64_t)(box_start[T + 1] - box_start[T]);
+      const uint32_t c = (uint32_t)__popcll(__ballot(found));
+      ns = wave_add63(ns);
+      sep = wave_max63(sep);
+      meet = wave_or63(meet);
+      if (lane == kWave - 1) {
+        const int32_t nT = box_start[T + 1] - box_start[T];
+        cnt[T] = (int32_t)c;
+        src[T] = (int32_t)ns;
+        srcsum += ns;
+        slots += (uint64_t)ns * (uint64_t)nT;
+        msep = fmax(msep, sep);
+        overlap |= meet;
+      }
     }
   }
-  sl = wave_add(sl);
-  ss = wave_add(ss);
-  msep = wave_max(msep);
-  overlap = wave_or(overlap);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (overlap) atomicOr(&st[ST_OVERLAP], 1u);
-    if (sl) atomicAdd((unsigned long long*)&s64[S64_SLOTS], (unsigned long long)sl);
-    if (ss) atomicAdd((unsigned long long*)&s64[S64_SRCSUM], (unsigned long long)ss);
-    raise_u64(&s64[S64_MAXSEP], (uint64_t)__double_as_longlong(msep));
+  if (!FILL) {
+    auto add = [](uint64_t x, uint64_t y) { return x + y; };
+    slots = block_combine63(slots, ldsl, add);
+    srcsum = block_combine63(srcsum, ldsl, add);
+    msep = block_combine63(msep, ldsd, [](double x, double y) { return fmax(x, y); });
+    overlap = block_combine63(overlap, ldsu, [](uint32_t x, uint32_t y) { return x | y; });
+    if (threadIdx.x == 0) {
+      Partial& p = part[blockIdx.x];
+      p.slots = slots;
+      p.srcsum = srcsum;
+      p.maxsep = msep;
+      p.overlap = overlap;
+    }
   }
-}
-
-__global__ void __launch_bounds__(kBlock) k_nbr_fill(const uint64_t* __restrict__ box_key,
-                                                  const int32_t* __restrict__ box_start,
-                                                  const int32_t* __restrict__ perm, const int32_t* __restrict__ ids,
-                                                  const int32_t* __restrict__ nbr_start, int32_t nb, CellGrid grid,
-                                                  int32_t* __restrict__ nbr_idx) {
-  const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (T >= nb) return;
-  int32_t nbr[27];
-  const int c = neighbours(box_key, nb, grid, ids, perm[box_start[T]], nbr);
-  const int32_t o = nbr_start[T];
-  for (int e = 0; e < c; ++e) nbr_idx[o + e] = nbr[e];
 }
 
 // Fixed-point coordinates: X = rint(x * 2^-qexp), kept modulo 2^32.  Differences of
@@ -538,10 +627,10 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
                                                     const int32_t* __restrict__ box_start,
                                                     const int32_t* __restrict__ nbr_start,
                                                     const int32_t* __restrict__ nbr_idx, int32_t nb,
-                                                    unsigned long long* __restrict__ zero) {
+                                                    uint64_t* __restrict__ zero) {
   const int64_t T = (int64_t)blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long z = 0;
+  uint32_t z = 0;
   if (T < nb) {
     for (int32_t t = box_start[T]; t < box_start[T + 1]; ++t) {
       const double x = sx[t], y = sx[n + t], w = sx[2 * n + t];
@@ -552,8 +641,8 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
       }
     }
   }
-  z = wave_add(z);
-  if (lane == 0 && z) atomicAdd(zero, z);
+  z = wave_add63(z);
+  if (lane == kWave - 1 && z) atomicAdd((unsigned long long*)zero, (unsigned long long)z);
 }
 
 __global__ void __launch_bounds__(kBlock) k_box_ids(const double* __restrict__ xyz, int64_t n3, double ox, double oy,
@@ -579,7 +668,7 @@ namespace {
 struct Bump {
   // Carves aligned sub-arrays out of one allocation.
   char* base;
-  size_t off, cap;
+  size_t off;
   template <typename T>
   T* take(int64_t count) {
     off = (off + 255) & ~size_t(255);
@@ -591,19 +680,42 @@ struct Bump {
 
 template <typename F>
 size_t measure(F&& f) {
-  Bump b{nullptr, 0, 0};
+  Bump b{nullptr, 0};
   f(b);
   return (b.off + 255) & ~size_t(255);
 }
 
-p2p_status dev_alloc(void** p, size_t bytes, hipStream_t s) {
-  *p = nullptr;
-  if (bytes == 0) return P2P_OK;
-  hipError_t e = hipMallocAsync(p, bytes, s);
-  if (e != hipSuccess || !*p) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(P2P_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+p2p_status dev_alloc(void** p, size_t bytes) {
+  *p = dmem_alloc(bytes);
+  if (!*p) return fail(P2P_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  return P2P_OK;
+}
+
+// Scratch that goes back to the cache when the scope ends; waits for the stream
+// first so that no enqueued work still reads it.
+struct ScopedBlock {
+  void* p = nullptr;
+  hipStream_t s;
+  explicit ScopedBlock(hipStream_t st) : s(st) {}
+  ~ScopedBlock() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      dmem_free(p);
+    }
+  }
+};
+
+// Copies the device status block to the host (one copy through pinned memory)
+// and waits for it.
+p2p_status read_status(const DevStatus* dev, DevStatus* host, hipStream_t s) {
+  StagingLock st = staging(sizeof(DevStatus));
+  if (st.host) {
+    P2P_HIP(hipMemcpyAsync(st.host, dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    std::memcpy(host, st.host, sizeof(DevStatus));
+  } else {
+    P2P_HIP(hipMemcpyAsync(host, dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
   }
   return P2P_OK;
 }
@@ -624,18 +736,19 @@ int64_t table_cell_limit(int64_t n) { return std::max<int64_t>(16ll << 20, 8 * n
 
 p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids, hipStream_t s) {
   if (n == 0) return P2P_OK;
-  uint32_t* bad = nullptr;
-  p2p_status st = dev_alloc((void**)&bad, sizeof(uint32_t), s);
-  if (st != P2P_OK) return st;
-  P2P_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), s));
+  ScopedBlock blk(s);
+  p2p_status rc = dev_alloc(&blk.p, sizeof(DevStatus));
+  if (rc != P2P_OK) return rc;
+  DevStatus* status = (DevStatus*)blk.p;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, (uint32_t*)status,
+                     (int64_t)(sizeof(DevStatus) / sizeof(uint32_t)), nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
   hipLaunchKernelGGL(k_box_ids, dim3(grid_for(3 * n)), dim3(kBlock), 0, s, xyz, 3 * n, origin[0], origin[1], origin[2],
-                     h, ids, bad);
-  uint32_t hb = 0;
+                     h, ids, &status->st[ST_BAD_ID]);
   P2P_HIP(hipGetLastError());
-  P2P_HIP(hipMemcpyAsync(&hb, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipFreeAsync(bad, s));
-  P2P_HIP(hipStreamSynchronize(s));
-  if (hb) return fail(P2P_ERR_RANGE, "a coordinate is not finite or its box id falls outside [0, 2^21)");
+  DevStatus hs;
+  rc = read_status(status, &hs, s);
+  if (rc != P2P_OK) return rc;
+  if (hs.st[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a coordinate is not finite or its box id falls outside [0, 2^21)");
   return P2P_OK;
 }
 
@@ -658,31 +771,29 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     P->q_sorted = b.take<char>((int64_t)(n * (int64_t)P->max_rhs * cbytes));
     P->g_sorted = b.take<char>((int64_t)(n * (int64_t)P->max_rhs * cbytes));
   };
-  size_t bytes1 = measure(carve1);
-  p2p_status rc = dev_alloc(&P->arena, bytes1, s);
+  const size_t bytes1 = measure(carve1);
+  p2p_status rc = dev_alloc(&P->arena, bytes1);
   if (rc != P2P_OK) return rc;
   P->device_bytes = bytes1;
   {
-    Bump b{(char*)P->arena, 0, bytes1};
+    Bump b{(char*)P->arena, 0};
     carve1(b);
   }
-  if (n == 0) {
-    P2P_HIP(hipMemsetAsync(P->box_start, 0, sizeof(int32_t), s));
-    P2P_HIP(hipMemsetAsync(P->nbr_start, 0, sizeof(int32_t), s));
-    P2P_HIP(hipMemsetAsync(P->tile_start, 0, sizeof(int32_t), s));
-    P->qexp = -30;
-    P2P_HIP(hipStreamSynchronize(s));
-    return P2P_OK;
-  }
 
-  // ---- temporaries, freed before returning
+  // ---- the id range decides between the dense cell table and binary search;
+  //      it is known only after the first kernel, so the table is sized from the
+  //      first readback and allocated then.
   const int64_t g_rs = grid_for(n, kRsTile);
   const int64_t scan_parts = grid_for(std::max<int64_t>(256 * g_rs, n + 1), kScanTile);
-  uint64_t *k0, *k1, *s64;
-  int32_t *v1, *flag, *cnt, *src, *part32, *tot;
-  uint32_t *hist, *partu, *st;
-  double* bb;
+  uint64_t *k0 = nullptr, *k1 = nullptr;
+  int32_t *v1 = nullptr, *flag = nullptr, *cnt = nullptr, *src = nullptr, *part32 = nullptr;
+  uint32_t *hist = nullptr, *partu = nullptr;
+  double* bb = nullptr;
+  DevStatus* status = nullptr;
+  Partial* part = nullptr;
   auto carvet = [&](Bump& b) {
+    status = b.take<DevStatus>(1);
+    part = b.take<Partial>(kGridStride);
     k0 = b.take<uint64_t>(n);
     k1 = b.take<uint64_t>(n);
     v1 = b.take<int32_t>(n);
@@ -692,63 +803,62 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     hist = b.take<uint32_t>(256 * g_rs);
     partu = b.take<uint32_t>(scan_parts);
     part32 = b.take<int32_t>(scan_parts);
-    bb = b.take<double>(6 * n);
-    st = b.take<uint32_t>(ST_COUNT);
-    s64 = b.take<uint64_t>(S64_COUNT);
-    tot = b.take<int32_t>(2);
+    bb = b.take<double>(6 * std::max<int64_t>(n, 1));
   };
-  size_t bytest = measure(carvet);
-  void* tmp = nullptr;
-  rc = dev_alloc(&tmp, bytest, s);
+  ScopedBlock tmp(s), tbl(s);
+  rc = dev_alloc(&tmp.p, measure(carvet));
   if (rc != P2P_OK) return rc;
-  struct TmpGuard {
-    void* p;
-    hipStream_t s;
-    ~TmpGuard() {
-      if (p) (void)hipFreeAsync(p, s);
-    }
-  } guard{tmp, s}, guard_table{nullptr, s};
   {
-    Bump b{(char*)tmp, 0, bytest};
+    Bump b{(char*)tmp.p, 0};
     carvet(b);
   }
-  P2P_HIP(hipMemsetAsync(st, 0, sizeof(uint32_t) * ST_COUNT, s));
-  P2P_HIP(hipMemsetAsync(s64, 0, sizeof(uint64_t) * S64_COUNT, s));
-  P2P_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), s));
-  P2P_HIP(hipMemsetAsync(src, 0, sizeof(int32_t) * (n + 1), s));
+  // status block and partial rows are contiguous in the scratch block
+  const int64_t zero_words = (int64_t)(((char*)(part + kGridStride) - (char*)status) / sizeof(uint32_t));
+  hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n + 1))), dim3(kBlock), 0, s,
+                     (uint32_t*)status, zero_words, cnt, src, n + 1, nullptr, (int64_t)0);
+  if (n == 0) {  // offsets of an empty plan: box_start = nbr_start = tile_start = {0}
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, nullptr, (int64_t)0, P->box_start, P->nbr_start,
+                       (int64_t)1, nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, nullptr, (int64_t)0, P->tile_start, P->tile_start,
+                       (int64_t)1, nullptr, (int64_t)0);
+    P->qexp = -30;
+    P2P_HIP(hipGetLastError());
+    P2P_HIP(hipStreamSynchronize(s));
+    return P2P_OK;
+  }
 
   // ---- 1. Morton keys and validation (first readback)
-  hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, xyz, ids, n, k0, P->perm, st);
+  hipLaunchKernelGGL(k_keys, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n))), dim3(kBlock), 0, s, xyz, ids,
+                     n, k0, P->perm, part);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
-  uint32_t hst[ST_COUNT];
-  P2P_HIP(hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipStreamSynchronize(s));
-  if (hst[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a box id falls outside [0, 2^21)");
-  if (hst[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
+  DevStatus hs;
+  rc = read_status(status, &hs, s);
+  if (rc != P2P_OK) return rc;
+  if (hs.st[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a box id falls outside [0, 2^21)");
+  if (hs.st[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
 
   // dense cell table when the occupied id range is small enough
   CellGrid grid{nullptr, 0, 0, 0, 0, 0};
   {
-    const int32_t lo[3] = {(int32_t)(kIdMask - hst[ST_LO_X]), (int32_t)(kIdMask - hst[ST_LO_Y]),
-                           (int32_t)(kIdMask - hst[ST_LO_Z])};
-    const int64_t ext[3] = {(int64_t)hst[ST_HI_X] - lo[0] + 3, (int64_t)hst[ST_HI_Y] - lo[1] + 3,
-                            (int64_t)hst[ST_HI_Z] - lo[2] + 3};
+    const int32_t lo[3] = {(int32_t)(kIdMask - hs.st[ST_LO_X]), (int32_t)(kIdMask - hs.st[ST_LO_Y]),
+                           (int32_t)(kIdMask - hs.st[ST_LO_Z])};
+    const int64_t ext[3] = {(int64_t)hs.st[ST_HI_X] - lo[0] + 3, (int64_t)hs.st[ST_HI_Y] - lo[1] + 3,
+                            (int64_t)hs.st[ST_HI_Z] - lo[2] + 3};
     const double cells = (double)ext[0] * (double)ext[1] * (double)ext[2];
     if (cells <= (double)table_cell_limit(n)) {
-      void* tp = nullptr;
-      rc = dev_alloc(&tp, sizeof(int32_t) * (size_t)cells, s);
-      if (rc == P2P_OK) {
-        guard_table.p = tp;
-        P2P_HIP(hipMemsetAsync(tp, 0xff, sizeof(int32_t) * (size_t)cells, s));  // -1: no box
-        grid = CellGrid{(int32_t*)tp, lo[0], lo[1], lo[2], ext[0], ext[1]};
-      } else {
-        set_error("");  // no room for the table: fall back to binary search
+      tbl.p = dmem_alloc(sizeof(int32_t) * (size_t)cells);  // no room: fall back to binary search
+      if (tbl.p) {
+        grid = CellGrid{(int32_t*)tbl.p, lo[0], lo[1], lo[2], ext[0], ext[1]};
+        hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for((int64_t)cells))),
+                           dim3(kBlock), 0, s, nullptr, (int64_t)0, nullptr, nullptr, (int64_t)0, grid.table,
+                           (int64_t)cells);
       }
     }
   }
 
   // ---- 2. stable sort of the points by key, over the key bits in use
-  const int bits = 3 * bit_length(hst[ST_ID_OR]);
+  const int bits = 3 * bit_length(hs.st[ST_ID_OR]);
   bool second = false;
   rc = radix_sort(k0, P->perm, k1, v1, n, bits, hist, partu, &second, s);
   if (rc != P2P_OK) return rc;
@@ -756,49 +866,42 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   if (second) P2P_HIP(hipMemcpyAsync(P->perm, v1, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
 
   // ---- 3. box table: runs of equal keys
-  int32_t* dnb = flag + n;  // scan total = number of boxes
   hipLaunchKernelGGL(k_box_flags, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag);
-  rc = scan<int32_t>(flag, flag, n, part32, dnb, s);
+  rc = scan<int32_t>(flag, flag, n, part32, &status->nbox, s);
   if (rc != P2P_OK) return rc;
-  hipLaunchKernelGGL(k_box_write, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag, P->perm, ids, P->box_key,
-                     P->box_start, dnb, grid);
+  hipLaunchKernelGGL(k_box_write, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag, P->box_key, P->box_start,
+                     status, grid);
   const unsigned gs = (unsigned)std::min<int64_t>(kGridStride, grid_for(n, kWavesPerBlockPlan));
-  hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, dnb, P->sx64, bb, st,
-                     s64);
+  hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, status, P->sx64, bb,
+                     part);
 
   // ---- 4. neighbour counts, neighbourhood source counts, separation bound.
   //         Entries past the last box stay zero, so scanning n entries gives the
   //         offsets of the B boxes and, at index B, the totals.
-  const unsigned gt = (unsigned)std::min<int64_t>(kGridStride, grid_for(n));
-  hipLaunchKernelGGL(k_nbr_count, dim3(gt), dim3(kBlock), 0, s, P->box_key, P->box_start, P->perm, ids, bb, dnb, grid,
-                     cnt, src, s64, st);
+  hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
+                     nullptr, nullptr, part);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
-  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, tot, s);  // tot[0] = list entries
+  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, &status->nnz, s);
   if (rc != P2P_OK) return rc;
   rc = scan<int32_t>(src, P->tile_start, n + 1, part32, nullptr, s);
   if (rc != P2P_OK) return rc;
 
   // second readback: sizes of the lists and the geometry bounds
-  int32_t hB = 0, hnnz = 0;
-  uint64_t h64[S64_COUNT];
-  P2P_HIP(hipMemcpyAsync(&hB, dnb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipMemcpyAsync(&hnnz, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipMemcpyAsync(h64, s64, sizeof(h64), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipMemcpyAsync(hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipStreamSynchronize(s));
-  const int32_t B = hB;
+  rc = read_status(status, &hs, s);
+  if (rc != P2P_OK) return rc;
+  const int32_t B = hs.nbox;
   P->B = B;
-  P->nnz = hnnz;
-  P->n_slots = (int64_t)h64[S64_SLOTS];
-  P->t_max = (int32_t)hst[ST_TMAX];
-  P->may_coincide = hst[ST_OVERLAP] != 0;
-  const int64_t srclen = (int64_t)h64[S64_SRCSUM];
+  P->nnz = hs.nnz;
+  P->n_slots = (int64_t)hs.slots;
+  P->t_max = (int32_t)hs.st[ST_TMAX];
+  P->may_coincide = hs.st[ST_OVERLAP] != 0;
   double sep, xabs;
-  std::memcpy(&sep, &h64[S64_MAXSEP], sizeof(double));
-  std::memcpy(&xabs, &h64[S64_MAXABS], sizeof(double));
+  std::memcpy(&sep, &hs.maxsep, sizeof(double));
+  std::memcpy(&xabs, &hs.maxabs, sizeof(double));
   P->max_sep = sep;
-  if (srclen > 0x7fffffffll) return fail(P2P_ERR_RANGE, "the per-box source lists exceed 2^31 entries");
-  P->tile_len = tiles ? srclen : 0;
+  if ((int64_t)hs.srcsum > 0x7fffffffll) return fail(P2P_ERR_RANGE, "the per-box source lists exceed 2^31 entries");
+  P->tile_len = tiles ? (int64_t)hs.srcsum : 0;
   P->max_turns = P->k * std::sqrt(3.0) * sep / (2.0 * M_PI);
 
   // ---- 5. quantum of the FP32 coordinates: 2^qexp with sep < 2^(qexp + 30), so a
@@ -820,16 +923,17 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
     P->tile_x64 = (tiles && f64) ? b.take<double>(3 * P->tile_len) : nullptr;
     P->tile_x32 = (tiles && !f64) ? b.take<int32_t>(3 * P->tile_len) : nullptr;
   };
-  size_t bytes2 = measure(carve2);
-  rc = dev_alloc(&P->arena2, bytes2, s);
+  const size_t bytes2 = measure(carve2);
+  rc = dev_alloc(&P->arena2, bytes2);
   if (rc != P2P_OK) return rc;
   P->device_bytes += bytes2;
   {
-    Bump b{(char*)P->arena2, 0, bytes2};
+    Bump b{(char*)P->arena2, 0};
     carve2(b);
   }
-  hipLaunchKernelGGL(k_nbr_fill, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_key, P->box_start, P->perm, ids,
-                     P->nbr_start, B, grid, P->nbr_idx);
+  hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
+                     dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
+                     P->nbr_idx, part);
   if (!f64) hipLaunchKernelGGL(k_fixed, dim3(grid_for(3 * n)), dim3(kBlock), 0, s, P->sx64, 3 * n, P->qexp, P->sx32);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
@@ -853,19 +957,20 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
 
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   if (P->n_pairs >= 0) return P2P_OK;
-  unsigned long long* z = nullptr;
-  p2p_status rc = dev_alloc((void**)&z, sizeof(unsigned long long), s);
+  ScopedBlock blk(s);
+  p2p_status rc = dev_alloc(&blk.p, sizeof(DevStatus));
   if (rc != P2P_OK) return rc;
-  P2P_HIP(hipMemsetAsync(z, 0, sizeof(unsigned long long), s));
+  DevStatus* status = (DevStatus*)blk.p;
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, (uint32_t*)status,
+                     (int64_t)(sizeof(DevStatus) / sizeof(uint32_t)), nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
   if (P->B > 0)
     hipLaunchKernelGGL(k_count_zero, dim3(grid_for(P->B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx64, P->n,
-                       P->box_start, P->nbr_start, P->nbr_idx, (int32_t)P->B, z);
-  unsigned long long hz = 0;
+                       P->box_start, P->nbr_start, P->nbr_idx, (int32_t)P->B, &status->zero);
   P2P_HIP(hipGetLastError());
-  P2P_HIP(hipMemcpyAsync(&hz, z, sizeof(hz), hipMemcpyDeviceToHost, s));
-  P2P_HIP(hipFreeAsync(z, s));
-  P2P_HIP(hipStreamSynchronize(s));
-  P->n_zero = (int64_t)hz;
+  DevStatus hs;
+  rc = read_status(status, &hs, s);
+  if (rc != P2P_OK) return rc;
+  P->n_zero = (int64_t)hs.zero;
   P->n_pairs = P->n_slots - P->n_zero;
   return P2P_OK;
 }

@@ -67,7 +67,6 @@ struct F32 {
     }
     return g;
   }
-  __device__ static __forceinline__ float sum(float v) { return wave_sum(v); }
 };
 
 struct F64 {
@@ -99,7 +98,6 @@ struct F64 {
     }
     return g;
   }
-  __device__ static __forceinline__ double sum(double v) { return wave_sum(v); }
 };
 
 // ---------------------------------------------------------------------------
@@ -175,6 +173,14 @@ __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, 
   wave_lds_sync();
 }
 
+// Per-wavefront LDS of a sweep: the target sums of the current block of 64
+// targets and, for the CSR layout, the source indices of the current group.
+template <class Tr, class Op, bool CSR>
+struct SweepLds {
+  typename Tr::real sums[Op::NA][kWave];
+  int32_t idx[CSR ? kWave * Tr::K : 1];
+};
+
 // The sweep.  Op supplies:
 //   NP, NT, NA            payload reals per source, per target, accumulators
 //   load_src(p, pay)      payload of the source at sorted position p
@@ -182,7 +188,7 @@ __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, 
 //   pair<HELM>(geo, spay, tpay, acc)
 //   store(t, acc)         final values of target t (sorted position), by its lane
 template <class Tr, class Op, bool HELM, bool CSR>
-__device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int32_t* lds) {
+__device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, SweepLds<Tr, Op, CSR>& L) {
   using real = typename Tr::real;
   using coord = typename Tr::coord;
   constexpr int K = Tr::K;
@@ -206,12 +212,9 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int3
   const int64_t n = G.n, tl = G.tl;
   for (int32_t tb = t0; tb < t1; tb += kWave) {
     const int32_t te = min(tb + kWave, t1);
-    real mine[NA];  // lane l: target tb + l
-#pragma unroll
-    for (int a = 0; a < NA; ++a) mine[a] = real(0);
     for (int32_t sg = s0; sg < s1; sg += kWave * K) {
       const int nch = min(K, (s1 - sg + kWave - 1) / kWave);
-      if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, lds, lane);
+      if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, L.idx, lane);
       coord X[K], Y[K], Z[K];
       real P[K][NP > 0 ? NP : 1];
 #pragma unroll
@@ -226,7 +229,7 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int3
         if (c < nch) {
           int32_t p;
           if (CSR) {
-            p = lds[ok ? e - sg : 0];
+            p = L.idx[ok ? e - sg : 0];
             X[c] = G.sx[p];
             Y[c] = G.sx[n + p];
             Z[c] = G.sx[2 * n + p];
@@ -240,8 +243,16 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int3
           if (ok) op.load_src(p, P[c]);
         }
       }
+      const bool first_group = sg == s0;
+      // target coordinates are fetched one target ahead
+      coord nx = ld_uniform(G.sx + tb), ny = ld_uniform(G.sx + n + tb), nz = ld_uniform(G.sx + 2 * n + tb);
       for (int32_t t = tb; t < te; ++t) {
-        const coord px = ld_uniform(G.sx + t), py = ld_uniform(G.sx + n + t), pz = ld_uniform(G.sx + 2 * n + t);
+        const coord px = nx, py = ny, pz = nz;
+        if (t + 1 < te) {
+          nx = ld_uniform(G.sx + t + 1);
+          ny = ld_uniform(G.sx + n + t + 1);
+          nz = ld_uniform(G.sx + 2 * n + t + 1);
+        }
         real tp[NT > 0 ? NT : 1];
         op.load_tgt(t, tp);
         real acc[NA];
@@ -262,14 +273,22 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, int3
             }
           }
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const real v = Tr::sum(acc[a]);
-          if (lane == t - tb) mine[a] += v;
+        for (int a = 0; a < NA; ++a) acc[a] = wave_sum63(acc[a]);
+        if (lane == kWave - 1) {
+#pragma unroll
+          for (int a = 0; a < NA; ++a) L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
         }
       }
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
     }
-    if (tb + lane < te) op.store(tb + lane, mine);
+    wave_lds_sync();
+    if (tb + lane < te) {
+      real mine[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) mine[a] = L.sums[a][lane];
+      op.store(tb + lane, mine);
+    }
+    wave_lds_sync();  // the sums are rewritten by the next block of targets
   }
 }
 
