@@ -6,8 +6,10 @@ Workload: 2M points uniform on the unit sphere, leaf boxes sized for ~32 points
 per non-empty box, k = 2 pi * 64, complex64 strengths ~ N(0,1), one right-hand
 side (seeded, synthetic).  One step is one pass of the whole path on that input,
 already resident in HBM: leaf-box ids from the positions, the plan build (Morton
-keys, sort, box table, neighbour lists, replicated source lists), the FP32 apply
-y = A_near q, and the plan's release.
+keys, sort, box table, neighbour lists; replicated source lists for the tiles
+layout), the FP32 apply y = A_near q, and the plan's release.  The step uses the
+non-redundant CSR layout unless --layout tiles is given; the other layout is
+timed beside it.
 
 Printed: one JSON line.  value = near-field interactions (ordered pairs with
 r != 0) per second of the whole step.  Besides it: the apply alone, the FP64 path
@@ -43,7 +45,7 @@ CUS, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
 PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_tiles_sphere2M_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_counters.md")
 KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
                   "paper_2403_01596_amd/csrc/common.h"]
 
@@ -61,8 +63,8 @@ def kernel_source_digest() -> str:
 
 
 def stored_traffic():
-    """HBM bytes per sweep launch from the committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
+    """HBM bytes per launch of the FP32 CSR sweep from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
     try:
         text = open(COUNTERS_FILE).read()
     except OSError:
@@ -81,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--layout", choices=["csr", "tiles"], default="csr",
+                    help="source layout of the timed step and of the roofline kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--sweep-only", action="store_true",
@@ -117,7 +121,7 @@ def main():
 
     if args.sweep_only:
         ids = p2p.box_ids(xyz, origin, inst.h)
-        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
         for _ in range(args.apply_reps):
             plan.apply(q32)
         torch.cuda.synchronize()
@@ -127,7 +131,7 @@ def main():
 
     def step():
         ids = p2p.box_ids(xyz, origin, inst.h)
-        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
         y = plan.apply(q32)
         plan.close()
         return y
@@ -151,7 +155,7 @@ def main():
         ids_b = p2p.box_ids(xyz, origin, inst.h)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pl = p2p.Plan(xyz, ids_b, inst.k, dtype=torch.complex64, layout="tiles")
+        pl = p2p.Plan(xyz, ids_b, inst.k, dtype=torch.complex64, layout=args.layout)
         t2 = time.perf_counter()
         pl.apply(q32)
         torch.cuda.synchronize()
@@ -166,7 +170,7 @@ def main():
     ids = p2p.box_ids(xyz, origin, inst.h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan32 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="tiles")
+    plan32 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
     plan_s = time.perf_counter() - t0
     info = plan32.info()
     n_pairs = info["n_pairs"]
@@ -186,22 +190,23 @@ def main():
         plan.timing(False)
         return out, e0.elapsed_time(e1) / reps, sweep_ms / calls
 
+    other = "tiles" if args.layout == "csr" else "csr"
     y32, apply32_ms, sweep32_ms = time_apply(plan32, q32, args.apply_reps)
-    log("f32 tiles: apply %.3f ms, sweep kernel %.3f ms" % (apply32_ms, sweep32_ms))
-    plan_csr = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="csr")
-    _, apply_csr_ms, sweep_csr_ms = time_apply(plan_csr, q32, max(3, args.apply_reps // 4))
-    plan_csr.close()
-    log("f32 csr: apply %.3f ms, sweep kernel %.3f ms" % (apply_csr_ms, sweep_csr_ms))
-    plan64 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex128, layout="tiles")
+    log("f32 %s: apply %.3f ms, sweep kernel %.3f ms" % (args.layout, apply32_ms, sweep32_ms))
+    plan_o = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=other)
+    _, apply_o_ms, sweep_o_ms = time_apply(plan_o, q32, max(3, args.apply_reps // 4))
+    plan_o.close()
+    log("f32 %s: apply %.3f ms, sweep kernel %.3f ms" % (other, apply_o_ms, sweep_o_ms))
+    plan64 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex128, layout=args.layout)
     y64, apply64_ms, sweep64_ms = time_apply(plan64, q64, max(3, args.apply_reps // 4))
     plan64.close()
-    log("f64 tiles: apply %.3f ms, sweep kernel %.3f ms" % (apply64_ms, sweep64_ms))
+    log("f64 %s: apply %.3f ms, sweep kernel %.3f ms" % (args.layout, apply64_ms, sweep64_ms))
 
     achieved = n_pairs / (sweep32_ms * 1e-3) / 1e9
-    traffic = stored_traffic()
+    traffic = stored_traffic() if args.layout == "csr" else None
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_GPAIRS, 1), "unit": "Gpair/s",
                 "frac": round(achieved / PEAK_GPAIRS, 4), "traffic": traffic,
-                "kernel": "sweep FP32 tiles (k_apply<F32,helmholtz,tiles>)",
+                "kernel": "sweep FP32 %s (k_apply<F32,helmholtz,%s>)" % (args.layout, args.layout),
                 "work_per_pair": "15 VALU + 3 transcendental = %d issue slots" % SLOTS_PER_PAIR,
                 "pairs_per_launch": n_pairs, "kernel_ms": round(sweep32_ms, 4)}
 
@@ -245,21 +250,20 @@ def main():
         "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": inst.name, "n_points": inst.n, "k": inst.k, "leaf_h": inst.h,
-                   "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": "tiles",
+                   "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": args.layout,
                    "step": "box ids + plan build + FP32 apply + release"},
         "rel_err": errs or None,
         "n_pairs": n_pairs,
-        "apply": {"f32_tiles_gpairs_s": round(n_pairs / apply32_ms / 1e6, 2),
-                  "f32_csr_gpairs_s": round(n_pairs / apply_csr_ms / 1e6, 2),
-                  "f64_tiles_gpairs_s": round(n_pairs / apply64_ms / 1e6, 2),
-                  "f32_tiles_ms": round(apply32_ms, 4), "f32_csr_ms": round(apply_csr_ms, 4),
-                  "f64_tiles_ms": round(apply64_ms, 4),
-                  "sweep_ms": {"f32_tiles": round(sweep32_ms, 4), "f32_csr": round(sweep_csr_ms, 4),
-                               "f64_tiles": round(sweep64_ms, 4)}},
+        "apply": {"f32_%s_gpairs_s" % args.layout: round(n_pairs / apply32_ms / 1e6, 2),
+                  "f32_%s_gpairs_s" % other: round(n_pairs / apply_o_ms / 1e6, 2),
+                  "f64_%s_gpairs_s" % args.layout: round(n_pairs / apply64_ms / 1e6, 2),
+                  "f32_%s_ms" % args.layout: round(apply32_ms, 4), "f32_%s_ms" % other: round(apply_o_ms, 4),
+                  "f64_%s_ms" % args.layout: round(apply64_ms, 4),
+                  "sweep_ms": {"f32_" + args.layout: round(sweep32_ms, 4), "f32_" + other: round(sweep_o_ms, 4),
+                               "f64_" + args.layout: round(sweep64_ms, 4)}},
         "plan_ms": round(plan_s * 1e3, 3),
         "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "tile_entries": info["tile_entries"],
-                 "device_bytes": info["device_bytes"]},
+        "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

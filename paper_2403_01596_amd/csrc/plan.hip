@@ -248,44 +248,35 @@ struct Partial {
   double maxsep, maxabs;
 };
 
+__device__ __forceinline__ void fold_into(Partial& a, const Partial& p) {
+  a.bad |= p.bad;
+  a.id_or |= p.id_or;
+  for (int d = 0; d < 3; ++d) {
+    a.lo[d] = max(a.lo[d], p.lo[d]);
+    a.hi[d] = max(a.hi[d], p.hi[d]);
+  }
+  a.tmax = max(a.tmax, p.tmax);
+  a.overlap |= p.overlap;
+  a.slots += p.slots;
+  a.srcsum += p.srcsum;
+  a.maxsep = fmax(a.maxsep, p.maxsep);
+  a.maxabs = fmax(a.maxabs, p.maxabs);
+}
+
+// One workgroup: every thread folds a stride of rows, then a tree over the threads.
 __global__ void __launch_bounds__(kBlock) k_fold(const Partial* __restrict__ part, int rows,
                                               DevStatus* __restrict__ status) {
   __shared__ Partial acc[kBlock];
   Partial a{};
-  for (int r = threadIdx.x; r < rows; r += kBlock) {
-    const Partial& p = part[r];
-    a.bad |= p.bad;
-    a.id_or |= p.id_or;
-    for (int d = 0; d < 3; ++d) {
-      a.lo[d] = max(a.lo[d], p.lo[d]);
-      a.hi[d] = max(a.hi[d], p.hi[d]);
-    }
-    a.tmax = max(a.tmax, p.tmax);
-    a.overlap |= p.overlap;
-    a.slots += p.slots;
-    a.srcsum += p.srcsum;
-    a.maxsep = fmax(a.maxsep, p.maxsep);
-    a.maxabs = fmax(a.maxabs, p.maxabs);
-  }
+  for (int r = threadIdx.x; r < rows; r += kBlock) fold_into(a, part[r]);
   acc[threadIdx.x] = a;
   __syncthreads();
+  for (int half = kBlock / 2; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half) fold_into(acc[threadIdx.x], acc[threadIdx.x + half]);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    Partial t{};
-    for (int i = 0; i < kBlock; ++i) {
-      const Partial& p = acc[i];
-      t.bad |= p.bad;
-      t.id_or |= p.id_or;
-      for (int d = 0; d < 3; ++d) {
-        t.lo[d] = max(t.lo[d], p.lo[d]);
-        t.hi[d] = max(t.hi[d], p.hi[d]);
-      }
-      t.tmax = max(t.tmax, p.tmax);
-      t.overlap |= p.overlap;
-      t.slots += p.slots;
-      t.srcsum += p.srcsum;
-      t.maxsep = fmax(t.maxsep, p.maxsep);
-      t.maxabs = fmax(t.maxabs, p.maxabs);
-    }
+    const Partial& t = acc[0];
     status->st[ST_BAD_ID] = t.bad & 1u;
     status->st[ST_BAD_X] = (t.bad >> 1) & 1u;
     status->st[ST_ID_OR] = t.id_or;
