@@ -45,6 +45,11 @@ CUS, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
 PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
 
+# Multi-RHS product: one complex multiply-add per (pair, right-hand side) = 8 real
+# flops on the FP32 matrix cores (dense FP32 MFMA peak 157.3 TFLOP/s).
+FLOPS_PER_PAIR_RHS = 8
+PEAK_MFMA_F32 = 157.3e12
+
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_counters.md")
 KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
                   "paper_2403_01596_amd/csrc/common.h"]
@@ -76,6 +81,76 @@ def stored_traffic():
     return float(b.group(1))
 
 
+def measure_mrhs(p2p, W, torch, reps, with_oracle):
+    """1M sphere points at ~32 per box (k = 2 pi 32) plus 16 uneven sphere instances of
+    10k..200k points, 64 complex64 right-hand sides each, all in one captured launch."""
+    m = 64
+    insts = [W.multi_rhs_main(m)] + W.multi_rhs_batch(m)
+    log("multi-RHS batch: %d instances, %d points" % (len(insts), sum(i.n for i in insts)))
+    plans, qs = [], []
+    for inst in insts:
+        xyz = torch.from_numpy(inst.xyz).cuda()
+        ids = torch.from_numpy(inst.ids).cuda()
+        plans.append(p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout="csr", max_rhs=m))
+        qs.append(torch.from_numpy(inst.q).cuda())
+    ys = [torch.empty_like(q) for q in qs]
+    batch = p2p.Batch(plans, m)
+    shape = batch.tune(qs, ys)
+    n_pairs = sum(pl.info()["n_pairs"] for pl in plans)
+    # kernel time: events around the product kernel (eager calls)
+    batch.timing(True)
+    for _ in range(reps):
+        batch.apply_into(qs, ys)
+    torch.cuda.synchronize()
+    kern_ms, calls = batch.timing_read()
+    batch.timing(False)
+    kern_ms /= calls
+    # one captured launch (gather + product), replayed
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.apply_into(qs, ys)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        batch.apply_into(qs, ys)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / reps
+    out = {"workload": "sphere1M_D32_k64pi + 16 uneven sphere instances (10k..200k), 64 complex64 RHS",
+           "instances": len(insts), "points": sum(i.n for i in insts), "rhs": m, "n_pairs": n_pairs,
+           "launch_shape": {"rhs_per_item": shape[0], "waves_per_block": shape[1]},
+           "graph_ms": round(graph_ms, 4), "kernel_ms": round(kern_ms, 4),
+           "pair_rhs_per_s": round(n_pairs * m / (graph_ms * 1e-3), 1),
+           "roofline": {"bound": "mfma", "achieved": round(FLOPS_PER_PAIR_RHS * n_pairs * m / (kern_ms * 1e-3) / 1e12, 2),
+                        "peak": PEAK_MFMA_F32 / 1e12, "unit": "TFLOP/s",
+                        "frac": round(FLOPS_PER_PAIR_RHS * n_pairs * m / (kern_ms * 1e-3) / PEAK_MFMA_F32, 4),
+                        "traffic": None, "kernel": "k_mrhs (FP32 MFMA 16x16x4, CSR)"}}
+    if with_oracle:
+        import oracle
+        num = den = 0.0
+        for inst, y in zip(insts, ys):
+            rows = np.random.default_rng(1).choice(inst.n, min(inst.n, 400), replace=False)
+            ref = oracle.Plan(inst.ids).apply_rows(inst.xyz, inst.k, inst.q, rows)
+            got = y.cpu().numpy()[rows]
+            num += float(np.sum(np.abs(got - ref) ** 2))
+            den += float(np.sum(np.abs(ref) ** 2))
+        out["rel_err_sampled_rows"] = math.sqrt(num / den)
+    log("multi-RHS: graph %.3f ms, kernel %.3f ms, %.3g pair-RHS/s, %.1f%% of FP32 MFMA peak" % (
+        graph_ms, kern_ms, out["pair_rhs_per_s"], 100 * out["roofline"]["frac"]))
+    batch.close()
+    for pl in plans:
+        pl.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--no-mrhs", action="store_true", help="skip the multi-right-hand-side batch")
+    ap.add_argument("--mrhs-only", action="store_true", help="only the multi-right-hand-side batch")
     ap.add_argument("--layout", choices=["csr", "tiles"], default="csr",
                     help="source layout of the timed step and of the roofline kernel")
     ap.add_argument("--copy-probe", action="store_true",
@@ -110,6 +187,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copied 3 x %d bytes" % (a.numel() * 4))
+        return 0
+
+    if args.mrhs_only:
+        print(json.dumps(measure_mrhs(p2p, W, torch, args.apply_reps, not args.no_cpu)))
         return 0
 
     inst = W.sphere_2m()
@@ -242,6 +323,7 @@ def main():
                 "f64": float(np.linalg.norm(y64h - ref) / np.linalg.norm(ref))}
         log("oracle %.1f s on %d threads; rel L2 f32 %.3e f64 %.3e" % (cpu_s, threads, errs["f32"], errs["f64"]))
     plan32.close()
+    mrhs = None if args.no_mrhs else measure_mrhs(p2p, W, torch, max(3, args.apply_reps // 4), not args.no_cpu)
 
     value = n_pairs / step_s / 1e9
     line = {
@@ -266,6 +348,7 @@ def main():
         "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "multi_rhs": mrhs,
     }
     print(json.dumps(line))
     return 0

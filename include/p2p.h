@@ -143,6 +143,30 @@ p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, 
 p2p_status p2p_plan_timing(p2p_plan plan, int enable);
 p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls);
 
+/* Batches: several complex64 plans (same layout, FP32) served together for nrhs
+ * right-hand sides, with the near-field products on the matrix cores; every plan
+ * must have been created with max_rhs >= nrhs, and count <= 32.  The plans stay
+ * owned by the caller and must outlive the batch.  p2p_batch_apply(q, y): host
+ * arrays of count device pointers, q[i] and y[i] are [n_i, nrhs] complex64 in
+ * plan i's point order; one gather launch and one product launch, no
+ * allocation and no synchronisation (capturable in a HIP graph).  Plans created
+ * with max_rhs >= 16 use the same path from p2p_apply when nrhs >= 16. */
+typedef struct p2p_batch_s* p2p_batch;
+p2p_status p2p_batch_create(const p2p_plan* plans, int32_t count, int32_t nrhs, p2p_batch* out);
+p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y, void* stream);
+
+/* Autotuner: times each launch shape of the product kernel (right-hand sides per
+ * work item: 32 or 64; wavefronts per workgroup: 1, 2 or 4) on the given inputs,
+ * keeps the fastest for the batch, and records it in the text file cache_path
+ * (one line per workload key; NULL: no file).  A shape found in the file for the
+ * same key is taken without timing.  Synchronises stream.  chosen: NULL or
+ * int32[2] receiving (right-hand sides per item, wavefronts per workgroup). */
+p2p_status p2p_batch_tune(p2p_batch batch, const void* const* q, void* const* y, const char* cache_path,
+                          void* stream, int32_t* chosen);
+p2p_status p2p_batch_timing(p2p_batch batch, int enable);
+p2p_status p2p_batch_timing_read(p2p_batch batch, double* ms, int64_t* calls);
+p2p_status p2p_batch_destroy(p2p_batch batch);
+
 /* Frees the plan.  Synchronises the device first, so work already enqueued with
  * the plan finishes before its memory is released.  NULL is a no-op. */
 p2p_status p2p_plan_destroy(p2p_plan plan);

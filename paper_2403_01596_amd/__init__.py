@@ -64,13 +64,22 @@ def lib():
     L.p2p_apply.argtypes = [P, P, P, i32, ctypes.c_int, P]
     L.p2p_apply_backward.argtypes = [P, P, P, P, P, i32, ctypes.c_int, P]
     L.p2p_plan_destroy.argtypes = [P]
+    L.p2p_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), i32, i32, ctypes.POINTER(ctypes.c_void_p)]
+    L.p2p_batch_apply.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), P]
+    L.p2p_batch_tune.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                 ctypes.c_char_p, P, ctypes.POINTER(ctypes.c_int32)]
+    L.p2p_batch_timing.argtypes = [P, ctypes.c_int]
+    L.p2p_batch_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.p2p_batch_destroy.argtypes = [P]
     L.p2p_plan_timing.argtypes = [P, ctypes.c_int]
     L.p2p_plan_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
     for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
-                 "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read"):
+                 "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
+                 "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
+                 "p2p_batch_timing_read", "p2p_batch_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -200,6 +209,74 @@ class Plan:
         dt = P2P_C64 if self.dtype == torch.complex64 else P2P_C128
         _check(lib().p2p_apply_backward(self.handle, _ptr(q), _ptr(gy), _ptr(dq), _ptr(dx), m, dt, _stream()))
         return dq, dx
+
+
+class Batch:
+    """Several complex64 plans served together for nrhs right-hand sides on the matrix cores.
+
+    One gather and one product launch per apply, no allocation inside the library
+    call and no synchronisation, so apply_into can be captured in a graph.  The
+    plans must outlive the batch and must have been created with max_rhs >= nrhs.
+    """
+
+    def __init__(self, plans, nrhs: int):
+        self.plans = list(plans)
+        self.nrhs = int(nrhs)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().p2p_batch_create(arr, len(self.plans), self.nrhs, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise P2PError(6, "batch has been closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.p2p_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, name):
+        if len(ts) != len(self.plans):
+            raise ValueError("one %s per plan" % name)
+        out = []
+        for t, p in zip(ts, self.plans):
+            if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+                raise TypeError("%s must be contiguous complex64 CUDA tensors" % name)
+            if tuple(t.shape) != (p.n, self.nrhs):
+                raise ValueError("%s must be [n_i, nrhs]" % name)
+            out.append(t.data_ptr())
+        return (ctypes.c_void_p * len(out))(*out)
+
+    def apply_into(self, qs, ys):
+        _check(lib().p2p_batch_apply(self.handle, self._ptrs(qs, "q"), self._ptrs(ys, "y"), _stream()))
+        return ys
+
+    def apply(self, qs):
+        return self.apply_into(qs, [torch.empty_like(q) for q in qs])
+
+    def tune(self, qs, ys, cache_path: Optional[str] = None):
+        """Times the launch shapes on these inputs and keeps the fastest; returns (rhs per item, waves per block)."""
+        chosen = (ctypes.c_int32 * 2)()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().p2p_batch_tune(self.handle, self._ptrs(qs, "q"), self._ptrs(ys, "y"), path, _stream(), chosen))
+        return chosen[0], chosen[1]
+
+    def timing(self, enable: bool = True):
+        _check(lib().p2p_batch_timing(self.handle, 1 if enable else 0))
+
+    def timing_read(self):
+        ms, calls = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().p2p_batch_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(calls)))
+        return ms.value, calls.value
 
 
 def apply(plan: Plan, q: torch.Tensor) -> torch.Tensor:

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp2p.so")
-SOURCES = ["api.hip", "memory.hip", "plan.hip", "apply.hip", "backward.hip"]
+SOURCES = ["api.hip", "memory.hip", "plan.hip", "apply.hip", "backward.hip", "mrhs.hip", "batch.hip"]
 ARCH = os.environ.get("P2P_OFFLOAD_ARCH", "gfx950")
 
 

@@ -5,7 +5,7 @@
 #include <new>
 #include <string>
 
-#include "common.h"
+#include "mrhs.h"
 
 namespace p2p {
 
@@ -61,6 +61,7 @@ static p2p_status free_plan(p2p_plan_s* P) {
   (void)hipGetDevice(&cur);
   if (cur != P->device) (void)hipSetDevice(P->device);
   if (hipDeviceSynchronize() != hipSuccess) rc = fail(P2P_ERR_HIP, "hipDeviceSynchronize failed in destroy");
+  if (P->self_batch) batch_free(P->self_batch);
   drop_events(P);
   delete P->timed;
   dmem_free(P->arena);
@@ -138,6 +139,8 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
     return fail(P2P_ERR_NOMEM, "host allocation failed");
   }
   p2p_status rc = build_plan(P, xyz, box_ijk, (hipStream_t)stream);
+  if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin)
+    rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
   if (rc != P2P_OK) {
     std::string msg = g_last_error;
     free_plan(P);
@@ -197,6 +200,10 @@ p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dt
   p2p_status rc = check_call(plan, nrhs, dtype);
   if (rc != P2P_OK) return rc;
   if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
+  if (plan->self_batch && nrhs >= kMrhsMin) {
+    void* yy = y;
+    return batch_apply(plan->self_batch, &q, &yy, nrhs, (hipStream_t)stream, plan->timing, plan->timed);
+  }
   return launch_apply(plan, q, y, nrhs, (hipStream_t)stream);
 }
 

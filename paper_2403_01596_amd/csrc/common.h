@@ -41,6 +41,8 @@ struct DeviceArena {
 
 }  // namespace p2p
 
+struct p2p_batch_s;
+
 struct p2p_plan_s {
   uint64_t magic;
   int device;
@@ -77,6 +79,8 @@ struct p2p_plan_s {
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
   void* g_sorted;      // [n * max_rhs] complex
+  // complex64 plans with max_rhs >= 16: the matrix-core path for many right-hand sides
+  p2p_batch_s* self_batch;
   // diagnostics: event pairs around the sweep kernels
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* timed;

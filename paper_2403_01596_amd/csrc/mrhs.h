@@ -1,0 +1,65 @@
+// Multi-right-hand-side apply on the matrix cores and batches of instances
+// (internal to libp2p).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace p2p {
+
+constexpr int kMaxBatch = 32;  // instances per batch (their pointers travel as kernel arguments)
+constexpr int kMrhsMin = 16;   // right-hand sides from which p2p_apply uses the matrix cores
+
+// Geometry of one instance, in device memory, read by the batched kernels.
+struct InstDesc {
+  int64_t n, tl;
+  const int32_t* perm;
+  const int32_t* box_start;
+  const int32_t* nbr_start;
+  const int32_t* nbr_idx;
+  const int32_t* tile_start;
+  const int32_t* tsrc;
+  const int32_t* tx32;
+  const int32_t* sx32;
+  float2* q_sorted;  // the instance plan's scratch
+  float kturns;      // k * 2^qexp / (2 pi)
+  float scale;       // 2^-qexp / (4 pi)
+};
+
+// Per-call pointers and sizes, passed by value (so that a captured graph holds them).
+struct BatchIO {
+  const float2* q[kMaxBatch];
+  float2* y[kMaxBatch];
+  int64_t prefix[kMaxBatch + 1];  // running sum of n_i * m
+  int count;
+  int m;
+};
+
+// Item ranges of the eight XCDs.
+struct XcdSplit {
+  int64_t start[9];
+};
+
+struct MrhsSetup {
+  InstDesc* desc;  // device [count]
+  int4* items;     // device [nitems]
+  int64_t nitems;
+  XcdSplit split;
+  bool helm, csr;
+};
+
+InstDesc make_desc(const p2p_plan_s* P);
+p2p_status build_items(const std::vector<p2p_plan_s*>& plans, int m, int width, std::vector<int4>& items,
+                       XcdSplit& split);
+unsigned mrhs_grid(const XcdSplit& split, int wpb);
+p2p_status launch_mrhs(const MrhsSetup& S, const BatchIO& io, int width, int wpb, hipStream_t s,
+                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// batches (batch.hip)
+p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s** out);
+p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int m, hipStream_t s, bool timing,
+                       std::vector<std::pair<hipEvent_t, hipEvent_t>>* sink);
+void batch_free(p2p_batch_s* b);
+
+}  // namespace p2p
