@@ -5,7 +5,7 @@
 Each .hip source is compiled with hipcc for gfx950 and the objects are linked
 against the HIP runtime that PyTorch loads (so that one runtime serves both the
 tensors and the library).  Packed FP32 instructions are turned off for all
-device code.
+device code, and matrix-core instructions keep their accumulators in VGPRs.
 """
 from __future__ import annotations
 
@@ -38,6 +38,9 @@ def torch_lib_dir() -> str:
 def compile_flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core accumulators in ordinary VGPRs: the AGPR form made the
+            # register allocator copy every accumulator tile each loop trip
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I" + os.path.join(ROOT, "include")]
 
 

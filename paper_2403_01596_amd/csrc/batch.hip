@@ -94,8 +94,10 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
     return hip_fail(e, "hipMemcpy (batch tables)");
   }
   const bool csr = plans[0]->layout == P2P_LAYOUT_CSR;
-  b->set64 = MrhsSetup{(InstDesc*)base, (int4*)(base + off64), (int64_t)it64.size(), sp64, helm, csr};
-  b->set32 = MrhsSetup{(InstDesc*)base, (int4*)(base + off32), (int64_t)it32.size(), sp32, helm, csr};
+  bool small = true;  // every instance's strengths within 32-bit byte offsets
+  for (int i = 0; i < count; ++i) small = small && plans[i]->n * (int64_t)m * 8 < (int64_t(1) << 32);
+  b->set64 = MrhsSetup{(InstDesc*)base, (int4*)(base + off64), (int64_t)it64.size(), sp64, helm, csr, small};
+  b->set32 = MrhsSetup{(InstDesc*)base, (int4*)(base + off32), (int64_t)it32.size(), sp32, helm, csr, small};
   *out = b;
   return P2P_OK;
 }
@@ -105,11 +107,9 @@ static BatchIO make_io(const p2p_batch_s* b, const void* const* q, void* const* 
   std::memset(&io, 0, sizeof(io));
   io.count = b->count;
   io.m = m;
-  io.prefix[0] = 0;
   for (int i = 0; i < b->count; ++i) {
     io.q[i] = (const float2*)q[i];
     io.y[i] = (float2*)y[i];
-    io.prefix[i + 1] = io.prefix[i] + b->plans[i]->n * (int64_t)m;
   }
   return io;
 }
@@ -130,7 +130,6 @@ p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int
     (void)hipGetLastError();
     e0 = e1 = nullptr;
   }
-  // the events bracket the product kernel only (not the strength gather)
   p2p_status rc = run(b, io, b->width, b->wpb, s, e0, e1);
   if (e0) sink->emplace_back(e0, e1);
   return rc;

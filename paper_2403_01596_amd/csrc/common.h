@@ -136,6 +136,13 @@ __device__ __forceinline__ T ld_uniform(const T* p) {
   return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// Load through the global address space (a vector memory load that waits on the
+// vector counter only), for pointers the compiler sees as generic.
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // Sum over the 64 lanes of a wavefront, valid in lane 63 only; every lane must be
 // active.  Quad butterflies, then row shifts by 4 and 8 (lane 15 of each row holds
 // the row's sum), then the row broadcasts 15 and 31 (lane 63 gathers the four

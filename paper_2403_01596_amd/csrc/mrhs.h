@@ -22,16 +22,14 @@ struct InstDesc {
   const int32_t* tsrc;
   const int32_t* tx32;
   const int32_t* sx32;
-  float2* q_sorted;  // the instance plan's scratch
   float kturns;      // k * 2^qexp / (2 pi)
   float scale;       // 2^-qexp / (4 pi)
 };
 
-// Per-call pointers and sizes, passed by value (so that a captured graph holds them).
+// Per-call pointers, passed by value (so that a captured graph holds them).
 struct BatchIO {
   const float2* q[kMaxBatch];
   float2* y[kMaxBatch];
-  int64_t prefix[kMaxBatch + 1];  // running sum of n_i * m
   int count;
   int m;
 };
@@ -47,6 +45,7 @@ struct MrhsSetup {
   int64_t nitems;
   XcdSplit split;
   bool helm, csr;
+  bool off32;      // every instance's strengths span less than 4 GiB (32-bit byte offsets)
 };
 
 InstDesc make_desc(const p2p_plan_s* P);

@@ -1,0 +1,91 @@
+"""Full-size workloads, in the launch configurations the benchmark uses, against the
+FP64 oracle.
+
+- 4M points on the (1, 0.5, 0.25) ellipsoid at 16, 32 and 64 points per box with
+  k = pi / (2h), both layouts, FP32: pair counts exact, sampled rows row by row;
+- the multi-right-hand-side batch (1M sphere points plus 16 uneven instances,
+  64 columns each) in one tuned launch: sampled rows of every instance;
+- the 500k-point cube's reverse pass (dq and dx), FP32 and FP64, against the
+  oracle's full reverse pass.
+
+Bars: relative L2 error <= 1e-5 (FP32 path), <= 1e-12 (FP64 path).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_01596_amd as p2p
+import workloads as W
+from gpu_helpers import dev, gpu_plan, rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+
+
+@pytest.mark.parametrize("d", [16, 32, 64])
+def test_ellipsoid_4m(d):
+    inst = W.ellipsoid_4m(d)
+    print("ellipsoid 4M D=%d generated" % d, flush=True)
+    orc = oracle.Plan(inst.ids)
+    st = orc.stats(inst.xyz)
+    rows = np.random.default_rng(d).choice(inst.n, 1500, replace=False)
+    yref = orc.apply_rows(inst.xyz, inst.k, inst.q, rows)
+    xyz, ids, q = dev(inst.xyz, torch.float64), dev(inst.ids, torch.int32), dev(inst.q)
+    for layout in ("tiles", "csr"):
+        P = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=layout)
+        info = P.info()
+        assert info["n_boxes"] == orc.n_boxes and info["n_nbr"] == orc.n_nbr
+        assert info["n_pairs"] == st["n_pairs"] and info["t_max"] == st["t_max"]
+        y = P.apply(q)
+        torch.cuda.synchronize()
+        err = rel_l2(y.cpu().numpy()[rows], yref)
+        print("  %s: %d pairs, rel L2 on sampled rows %.3e" % (layout, info["n_pairs"], err), flush=True)
+        assert err <= TOL[torch.complex64]
+        P.close()
+
+
+def test_multi_rhs_batch_full(tmp_path):
+    m = 64
+    insts = [W.multi_rhs_main(m)] + W.multi_rhs_batch(m)
+    print("batch of %d instances generated" % len(insts), flush=True)
+    plans = [gpu_plan(i.xyz, i.ids, i.k, layout="csr", max_rhs=m) for i in insts]
+    qs = [dev(i.q) for i in insts]
+    ys = [torch.empty_like(q) for q in qs]
+    B = p2p.Batch(plans, m)
+    B.tune(qs, ys, str(tmp_path / "tune.txt"))
+    for y in ys:
+        y.fill_(float("nan"))
+    B.apply_into(qs, ys)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for j, (inst, y) in enumerate(zip(insts, ys)):
+        rows = np.random.default_rng(j).choice(inst.n, min(inst.n, 300), replace=False)
+        ref = oracle.Plan(inst.ids).apply_rows(inst.xyz, inst.k, inst.q, rows)
+        got = y.cpu().numpy()
+        assert np.isfinite(got).all()
+        err = rel_l2(got[rows], ref)
+        worst = max(worst, err)
+        assert err <= TOL[torch.complex64], (j, inst.n, err)
+    print("  worst per-instance rel L2 on sampled rows %.3e" % worst, flush=True)
+    B.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_cube_500k_reverse_pass():
+    inst = W.grad_cube_500k()
+    orc = oracle.Plan(inst.ids)
+    g64 = W.strengths(inst.n, 1, np.random.default_rng(5), np.complex128)
+    for dtype in (torch.complex64, torch.complex128):
+        npd = np.complex64 if dtype == torch.complex64 else np.complex128
+        q, g = inst.q.astype(npd), g64.astype(npd)
+        dq_ref, dx_ref = orc.backward(inst.xyz, inst.k, q, g)
+        P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout="csr")
+        dq, dx = P.backward(dev(q), dev(g))
+        torch.cuda.synchronize()
+        e_q = rel_l2(dq.cpu().numpy(), dq_ref)
+        e_x = rel_l2(dx.cpu().numpy(), dx_ref)
+        print("  %s dq %.3e dx %.3e" % (dtype, e_q, e_x), flush=True)
+        assert e_q <= TOL[dtype] and e_x <= TOL[dtype]
+        P.close()
