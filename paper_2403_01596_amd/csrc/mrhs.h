@@ -24,6 +24,7 @@ struct InstDesc {
   const int32_t* sx32;
   float kturns;      // k * 2^qexp / (2 pi)
   float scale;       // 2^-qexp / (4 pi)
+  int32_t may_coincide;  // points of distinct boxes may coincide
 };
 
 // Per-call pointers, passed by value (so that a captured graph holds them).
@@ -47,6 +48,10 @@ struct MrhsSetup {
   bool helm, csr;
   bool off32;      // every instance's strengths span less than 4 GiB (32-bit byte offsets)
 };
+
+// Launch variant for m right-hand sides: the fast form needs 32-bit offsets and
+// every item's columns inside [0, m).
+inline bool mrhs_fast(const MrhsSetup& S, int m, int width) { return S.off32 && m % width == 0; }
 
 InstDesc make_desc(const p2p_plan_s* P);
 p2p_status build_items(const std::vector<p2p_plan_s*>& plans, int m, int width, std::vector<int4>& items,

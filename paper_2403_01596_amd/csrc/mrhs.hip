@@ -35,14 +35,19 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kXcds = 8;
 constexpr int kStepSrc = 4;      // sources per MFMA step (the K of 16x16x4)
-constexpr int kGroupSrc = 512;   // neighbourhood entries staged in LDS at a time
+constexpr int kGroupSrc = 512;   // LDS slots per wavefront for staged neighbourhood entries
+constexpr int kGroupCap = kGroupSrc - 2 * kStepSrc;  // real entries per group (the rest: padding)
 
-// A group's neighbourhood entries {x, y, z, caller's row} into the wavefront's LDS,
-// entries [sg, ge) of box T's list: CSR walks the box's own points first, then
-// its neighbour boxes; TILES copies the box's replicated list.
-template <bool CSR>
-__device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, const InstDesc& D, int64_t n,
+// A group's neighbourhood entries into the wavefront's LDS: {x, y, z, r} with r the
+// source's row in the caller's array (FAST: its byte offset, row * m * 8).  Entries
+// [sg, ge) of box T's list: CSR walks the box's own points first, then its
+// neighbour boxes; TILES copies the box's replicated list.  The slots from ge - sg
+// to 8 past the next multiple of 8 repeat the first entry, so that steps and the
+// prefetch of the step after the last never read a slot that was not written.
+template <bool CSR, bool FAST>
+__device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, const InstDesc& D, int64_t n, int m,
                                             int4* ent, int lane) {
+  const uint32_t rs = FAST ? 8u * (uint32_t)m : 1u;
   if (CSR) {
     int32_t off = 0;
     const int32_t j0 = ld_uniform(D.nbr_start + T), j1 = ld_uniform(D.nbr_start + T + 1);
@@ -54,7 +59,7 @@ __device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, c
       for (int32_t e = lo + lane; e < hi; e += kWave) {
         const int32_t p = a + (e - off);
         ent[e - sg] = make_int4(ld_global(D.sx32 + p), ld_global(D.sx32 + n + p), ld_global(D.sx32 + 2 * n + p),
-                                ld_global(D.perm + p));
+                                (int32_t)((uint32_t)ld_global(D.perm + p) * rs));
       }
       off += len;
     }
@@ -62,32 +67,36 @@ __device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, c
     const int64_t tl = D.tl;
     for (int32_t e = sg + lane; e < ge; e += kWave)
       ent[e - sg] = make_int4(ld_global(D.tx32 + e), ld_global(D.tx32 + tl + e), ld_global(D.tx32 + 2 * tl + e),
-                              ld_global(D.perm + ld_global(D.tsrc + e)));
+                              (int32_t)((uint32_t)ld_global(D.perm + ld_global(D.tsrc + e)) * rs));
   }
+  wave_lds_sync();
+  const int32_t cnt = ge - sg, padded = ((cnt + 2 * kStepSrc - 1) & ~(2 * kStepSrc - 1)) + 2 * kStepSrc;
+  if (lane < padded - cnt) ent[cnt + lane] = ent[0];
   wave_lds_sync();
 }
 
-// One step's operands for a lane: its source (coordinates and caller's row) and
-// that source's strengths in the lane's column of every 16-column tile.
+// One step's operands for a lane: its source (coordinates and row) and that
+// source's strengths in the lane's column of every 16-column tile.
 template <int TILES16>
 struct StepSrc {
   int4 src;
   f2 q[TILES16];
 };
 
-// Strengths of the source in s.src, read straight from the caller's array: with
-// 32-bit byte offsets from a wave-uniform base when the array spans < 4 GiB.
-template <int TILES16, bool OFF32>
-__device__ __forceinline__ void load_q(StepSrc<TILES16>& s, const float2* qb, int m, const uint32_t (&colb)[TILES16]) {
-  if (OFF32) {
-    const uint32_t rb = (uint32_t)s.src.w * (uint32_t)m * 8u;
-    const char* base = reinterpret_cast<const char*>(qb);
+// Strengths of the source in s.src, read straight from the caller's array.  FAST:
+// one 32-bit byte offset from a wave-uniform base, the tiles 128 bytes apart
+// (immediate offsets).  Otherwise 64-bit addressing and clamped columns.
+template <int TILES16, bool FAST>
+__device__ __forceinline__ void load_q(StepSrc<TILES16>& s, const float2* qb, int m, uint32_t lcol,
+                                       const int32_t (&col)[TILES16]) {
+  if (FAST) {
+    const char* base = reinterpret_cast<const char*>(qb) + ((uint32_t)s.src.w + lcol);
 #pragma unroll
-    for (int q = 0; q < TILES16; ++q) s.q[q] = ld_global(reinterpret_cast<const f2*>(base + (rb + colb[q])));
+    for (int q = 0; q < TILES16; ++q) s.q[q] = ld_global(reinterpret_cast<const f2*>(base + 128 * q));
   } else {
     const f2* row = reinterpret_cast<const f2*>(qb) + (int64_t)s.src.w * m;
 #pragma unroll
-    for (int q = 0; q < TILES16; ++q) s.q[q] = ld_global(row + colb[q] / 8u);
+    for (int q = 0; q < TILES16; ++q) s.q[q] = ld_global(row + col[q]);
   }
 }
 
@@ -103,12 +112,14 @@ __device__ __forceinline__ void pin_step(StepSrc<TILES16>& s) {
 }
 
 // One step: the lane's kernel value, then three products per column tile.
-template <int TILES16, bool HELM>
+// MASK: the pair may be at distance zero or past the list's end (valid false);
+// then the kernel value is zero.
+template <int TILES16, bool HELM, bool MASK>
 __device__ __forceinline__ void mfma_step(const StepSrc<TILES16>& s, bool valid, int32_t tx, int32_t ty, int32_t tz,
                                           float kturns, f4 (&p1)[TILES16], f4 (&p2)[TILES16],
                                           f4 (&p3)[TILES16]) {
-  const F32::Geo g = F32::template geo<HELM, true>(tx, ty, tz, s.src.x, s.src.y, s.src.z, kturns);
-  const float w = valid ? g.rinv : 0.0f;
+  const F32::Geo g = F32::template geo<HELM, MASK>(tx, ty, tz, s.src.x, s.src.y, s.src.z, kturns);
+  const float w = (!MASK || valid) ? g.rinv : 0.0f;
   const float gr = g.c * w, gi = g.s * w;
   const float gs = gr + gi;
 #pragma unroll
@@ -120,7 +131,27 @@ __device__ __forceinline__ void mfma_step(const StepSrc<TILES16>& s, bool valid,
   }
 }
 
-template <int TILES16, bool HELM, bool CSR, bool OFF32>
+// Operands and accumulators of one wavefront's item.
+template <int TILES16>
+struct MrhsState {
+  StepSrc<TILES16> a, b;
+  f4 p1[TILES16], p2[TILES16], p3[TILES16];
+};
+
+// Two steps (8 entries from e0): the loads of each step are issued one step ahead.
+template <int TILES16, bool HELM, bool FAST, bool MASK>
+__device__ __forceinline__ void mrhs_block(MrhsState<TILES16>& S, const int4* ent, int32_t e0, int32_t cnt, int kk,
+                                           const float2* qb, int m, uint32_t lcol, const int32_t (&col)[TILES16],
+                                           int32_t tx, int32_t ty, int32_t tz, float kturns) {
+  S.b.src = ent[e0 + kStepSrc + kk];
+  load_q<TILES16, FAST>(S.b, qb, m, lcol, col);
+  mfma_step<TILES16, HELM, MASK>(S.a, e0 + kk < cnt, tx, ty, tz, kturns, S.p1, S.p2, S.p3);
+  S.a.src = ent[e0 + 2 * kStepSrc + kk];
+  load_q<TILES16, FAST>(S.a, qb, m, lcol, col);
+  mfma_step<TILES16, HELM, MASK>(S.b, e0 + kStepSrc + kk < cnt, tx, ty, tz, kturns, S.p1, S.p2, S.p3);
+}
+
+template <int TILES16, bool HELM, bool CSR, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __restrict__ desc,
                                               const int4* __restrict__ items, XcdSplit split, int wpb) {
   __shared__ int4 lds_ent[kWavesPerBlock][kGroupSrc];
@@ -154,49 +185,50 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
     s0 = ld_uniform(D.tile_start + T);
     s1 = ld_uniform(D.tile_start + T + 1);
   }
+  // entries [s0, s_self) are the box's own points (listed first); a zero distance
+  // can only occur there, unless points of distinct boxes may coincide
+  const int32_t s_self = D.may_coincide ? s1 : s0 + (bt1 - bt0);
   const int64_t n = D.n;
   const int i = lane & 15;    // target row of A, column of B
   const int kk = lane >> 4;   // source of the step
-  const bool tvalid = i < nt;
-  const int32_t t = t_first + (tvalid ? i : 0);
+  // rows past the tile's last target repeat its first; their sums are never stored
+  const int32_t t = t_first + (i < nt ? i : 0);
   const int32_t tx = ld_global(D.sx32 + t), ty = ld_global(D.sx32 + n + t), tz = ld_global(D.sx32 + 2 * n + t);
   const float kturns = D.kturns;
   const float2* qb = io.q[inst];
-  // byte offsets of the lane's columns; columns past the call's last one read that
-  // last column, and their sums are never stored
-  uint32_t colb[TILES16];
+  const uint32_t lcol = 8u * (uint32_t)(rg + i);
+  // general form: columns past the call's last one read that last column; their
+  // sums are never stored
+  int32_t col[TILES16];
 #pragma unroll
-  for (int q = 0; q < TILES16; ++q) colb[q] = 8u * (uint32_t)min(rg + i + 16 * q, m - 1);
+  for (int q = 0; q < TILES16; ++q) col[q] = min(rg + i + 16 * q, m - 1);
 
   // 3-multiplication complex product: with P1 = Gr Qr, P2 = Gi Qi and
   // P3 = (Gr + Gi)(Qr + Qi), Re Y = P1 - P2 and Im Y = P3 - P1 - P2.
-  f4 p1[TILES16], p2[TILES16], p3[TILES16];
+  MrhsState<TILES16> S;
 #pragma unroll
   for (int q = 0; q < TILES16; ++q) {
-    p1[q] = f4{0.f, 0.f, 0.f, 0.f};
-    p2[q] = f4{0.f, 0.f, 0.f, 0.f};
-    p3[q] = f4{0.f, 0.f, 0.f, 0.f};
+    S.p1[q] = f4{0.f, 0.f, 0.f, 0.f};
+    S.p2[q] = f4{0.f, 0.f, 0.f, 0.f};
+    S.p3[q] = f4{0.f, 0.f, 0.f, 0.f};
   }
   int4* ent = lds_ent[wv];
-  for (int32_t sg = s0; sg < s1; sg += kGroupSrc) {
-    const int32_t cnt = min(s1 - sg, kGroupSrc);
-    stage_group<CSR>(T, sg, sg + cnt, D, n, ent, lane);
-    // Two operand sets in flight: the loads of the next step are issued before
-    // the products of the current one.  Entries past the group's end reload its
-    // first entry and are given a zero kernel value.
-    StepSrc<TILES16> a, b;
-    a.src = ent[kk < cnt ? kk : 0];
-    load_q<TILES16, OFF32>(a, qb, m, colb);
-    pin_step<TILES16>(a);
-    for (int32_t e0 = 0; e0 < cnt; e0 += 2 * kStepSrc) {
-      const int32_t e1 = e0 + kStepSrc + kk, e2 = e0 + 2 * kStepSrc + kk;
-      b.src = ent[e1 < cnt ? e1 : 0];
-      load_q<TILES16, OFF32>(b, qb, m, colb);
-      mfma_step<TILES16, HELM>(a, tvalid && e0 + kk < cnt, tx, ty, tz, kturns, p1, p2, p3);
-      a.src = ent[e2 < cnt ? e2 : 0];
-      load_q<TILES16, OFF32>(a, qb, m, colb);
-      mfma_step<TILES16, HELM>(b, tvalid && e1 < cnt, tx, ty, tz, kturns, p1, p2, p3);
-    }
+  for (int32_t sg = s0; sg < s1; sg += kGroupCap) {
+    const int32_t cnt = min(s1 - sg, kGroupCap);
+    stage_group<CSR, FAST>(T, sg, sg + cnt, D, n, m, ent, lane);
+    S.a.src = ent[kk];
+    load_q<TILES16, FAST>(S.a, qb, m, lcol, col);
+    pin_step<TILES16>(S.a);
+    // Blocks that may meet a zero distance (the box's own points), then the plain
+    // blocks, then the block that reaches the padding: the first and last take the
+    // masked form.
+    const int32_t plain_from = max(0, s_self - sg);
+    int32_t e0 = 0;
+    for (; e0 < cnt && e0 < plain_from; e0 += 2 * kStepSrc)
+      mrhs_block<TILES16, HELM, FAST, true>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
+    for (; e0 + 2 * kStepSrc <= cnt; e0 += 2 * kStepSrc)
+      mrhs_block<TILES16, HELM, FAST, false>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
+    if (e0 < cnt) mrhs_block<TILES16, HELM, FAST, true>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
     wave_lds_sync();
   }
   // D[row][col]: lane j + 16 (row / 4), register row % 4
@@ -210,8 +242,8 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
 #pragma unroll
       for (int q = 0; q < TILES16; ++q) {
         const int c = rg + i + 16 * q;
-        const float re = p1[q][r] - p2[q][r];
-        const float im = p3[q][r] - p1[q][r] - p2[q][r];
+        const float re = S.p1[q][r] - S.p2[q][r];
+        const float im = S.p3[q][r] - S.p1[q][r] - S.p2[q][r];
         if (c < m) y[yi + c] = make_float2(re * sc, im * sc);
       }
     }
@@ -236,6 +268,7 @@ InstDesc make_desc(const p2p_plan_s* P) {
   d.sx32 = P->sx32;
   d.kturns = (float)(P->k * std::ldexp(1.0, P->qexp) / (2.0 * M_PI));
   d.scale = (float)(std::ldexp(1.0, -P->qexp) / (4.0 * M_PI));
+  d.may_coincide = P->may_coincide ? 1 : 0;
   return d;
 }
 
@@ -290,9 +323,10 @@ p2p_status launch_mrhs(const MrhsSetup& S, const BatchIO& io, int width, int wpb
   const unsigned g = mrhs_grid(S.split, wpb);
 #define P2P_MRHS(TL, H, C, O) \
   hipLaunchKernelGGL((k_mrhs<TL, H, C, O>), dim3(g), dim3(kBlock), 0, s, io, S.desc, S.items, S.split, wpb)
+  const bool fast = mrhs_fast(S, io.m, width);
 #define P2P_MRHS_O(TL, H, C) \
   do {                       \
-    if (S.off32)             \
+    if (fast)                \
       P2P_MRHS(TL, H, C, true); \
     else                     \
       P2P_MRHS(TL, H, C, false); \

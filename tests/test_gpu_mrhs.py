@@ -11,6 +11,7 @@ import torch
 import oracle
 import paper_2403_01596_amd as p2p
 import workloads as W
+from cases import plan_cases
 from gpu_helpers import dev, gpu_plan, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +37,27 @@ def test_single_plan_many_rhs(layout, m):
     # every column block on its own
     for c0 in range(0, m, 16):
         assert rel_l2(y.cpu().numpy()[:, c0:c0 + 16], yref[:, c0:c0 + 16]) <= TOL
+
+
+@pytest.mark.parametrize("case", list(plan_cases()), ids=lambda c: c[0])
+@pytest.mark.parametrize("layout", ["csr", "tiles"])
+@pytest.mark.parametrize("m", [64, 24])
+def test_plan_cases_many_rhs(case, layout, m):
+    """Every parity case on the matrix-core path: m = 64 takes the fast form (whole
+    64-column items, 32-bit offsets), m = 24 the general one (clamped columns).
+    Covers duplicates and coincident points across boxes (the masked form
+    everywhere), boxes over 16 targets, lists over one LDS group and one point."""
+    name, xyz, ids, k = case
+    q = strengths(xyz.shape[0], m, 9)
+    P = gpu_plan(xyz, ids, k, layout=layout, max_rhs=m)
+    y = P.apply(dev(q)).cpu().numpy()
+    yref = oracle.Plan(ids).apply(xyz, k, q)
+    if np.linalg.norm(yref) == 0:
+        assert np.all(y == 0)
+        return
+    err = rel_l2(y, yref)
+    print("%s %s m=%d rel L2 %.3e" % (name, layout, m, err), flush=True)
+    assert err <= TOL
 
 
 def test_many_rhs_laplace_and_dense_boxes():
