@@ -45,6 +45,14 @@ CUS, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9
 PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
 PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
 
+# Reverse pass (dq and dx together, FP32 Helmholtz), per pair: the geometry above
+# (3 differences, 3 for r^2, r, phase and reduction: 9 VALU + rsq, sin, cos), dq's
+# conj(G) g (2 + 4), u = conj(g_i) q_j + conj(g_j) q_i (8), (c + is)(ikr - 1) (3),
+# Re(G' u) (2), 1/r^3 (3) and the three dx multiply-adds (3): 34 VALU operations
+# plus 3 transcendentals = 40 issue slots.
+BWD_SLOTS_PER_PAIR = 34 + 2 * 3
+PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 982 Gpair/s
+
 # Multi-RHS product: one complex multiply-add per (pair, right-hand side) = 8 real
 # flops on the FP32 matrix cores (dense FP32 MFMA peak 157.3 TFLOP/s).
 FLOPS_PER_PAIR_RHS = 8
@@ -53,30 +61,33 @@ PEAK_MFMA_F32 = 157.3e12
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_counters.md")
 KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
                   "paper_2403_01596_amd/csrc/common.h"]
+MRHS_COUNTERS_FILE = os.path.join(ROOT, "profiles", "mrhs_f32_csr_batch17_counters.md")
+MRHS_SOURCES = ["paper_2403_01596_amd/csrc/mrhs.hip", "paper_2403_01596_amd/csrc/mrhs.h",
+                "paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/common.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
-    """HBM bytes per launch of the FP32 CSR sweep from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def stored_traffic(path=None, sources=None):
+    """HBM bytes per launch of a kernel from its committed counter summary, if the
+    summary was taken on the current kernel sources (else None)."""
     try:
-        text = open(COUNTERS_FILE).read()
+        text = open(path or COUNTERS_FILE).read()
     except OSError:
         return None
     m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != kernel_source_digest():
+    if not m or not b or m.group(1) != kernel_source_digest(sources):
         return None
     return float(b.group(1))
 
@@ -132,7 +143,8 @@ def measure_mrhs(p2p, W, torch, reps, with_oracle):
            "roofline": {"bound": "mfma", "achieved": round(FLOPS_PER_PAIR_RHS * n_pairs * m / (kern_ms * 1e-3) / 1e12, 2),
                         "peak": PEAK_MFMA_F32 / 1e12, "unit": "TFLOP/s",
                         "frac": round(FLOPS_PER_PAIR_RHS * n_pairs * m / (kern_ms * 1e-3) / PEAK_MFMA_F32, 4),
-                        "traffic": None, "kernel": "k_mrhs (FP32 MFMA 16x16x4, CSR)"}}
+                        "traffic": stored_traffic(MRHS_COUNTERS_FILE, MRHS_SOURCES),
+                        "kernel": "k_mrhs (FP32 MFMA 16x16x4, CSR)"}}
     if with_oracle:
         import oracle
         num = den = 0.0
@@ -151,6 +163,81 @@ def measure_mrhs(p2p, W, torch, reps, with_oracle):
     return out
 
 
+def measure_backward(p2p, W, torch, reps):
+    """Reverse pass (dq and dx in one sweep) on 500k uniform points in a 25^3 grid,
+    k = 2 pi * 16, FP32 and FP64, CSR layout; sweep kernel time from the library's
+    events."""
+    inst = W.grad_cube_500k()
+    xyz = torch.from_numpy(inst.xyz).cuda()
+    ids = torch.from_numpy(inst.ids).cuda()
+    g64 = W.strengths(inst.n, 1, np.random.default_rng(5), np.complex128)
+    out = {"workload": "cube500k_g25 (500k uniform points, 25^3 boxes, k = 2 pi 16), dq and dx"}
+    for dt, name in ((torch.complex64, "f32"), (torch.complex128, "f64")):
+        q = torch.from_numpy(inst.q.astype(np.complex64 if name == "f32" else np.complex128)).cuda()
+        g = torch.from_numpy(g64.astype(np.complex64 if name == "f32" else np.complex128)).cuda()
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=dt, layout="csr")
+        n_pairs = plan.info()["n_pairs"]
+        plan.backward(q, g)
+        torch.cuda.synchronize()
+        plan.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.backward(q, g)
+        e1.record()
+        torch.cuda.synchronize()
+        kern_ms, calls = plan.timing_read()
+        plan.timing(False)
+        kern_ms /= calls
+        call_ms = e0.elapsed_time(e1) / reps
+        out[name] = {"n_pairs": n_pairs, "call_ms": round(call_ms, 4), "kernel_ms": round(kern_ms, 4),
+                     "gpairs_s": round(n_pairs / kern_ms / 1e6, 2)}
+        plan.close()
+    out["roofline_f32"] = {"bound": "alu", "achieved": out["f32"]["gpairs_s"], "peak": round(PEAK_BWD_GPAIRS, 1),
+                           "unit": "Gpair/s", "frac": round(out["f32"]["gpairs_s"] / PEAK_BWD_GPAIRS, 4),
+                           "work_per_pair": "34 VALU + 3 transcendental = %d issue slots" % BWD_SLOTS_PER_PAIR}
+    log("backward: f32 %.3f ms (%.1f Gpair/s, %.1f%% of its ALU roofline), f64 %.3f ms" % (
+        out["f32"]["kernel_ms"], out["f32"]["gpairs_s"], 100 * out["roofline_f32"]["frac"], out["f64"]["kernel_ms"]))
+    return out
+
+
+def measure_layouts(p2p, W, torch, reps):
+    """The two source layouts on 4M points of the (1, 0.5, 0.25) ellipsoid at 16, 32
+    and 64 points per box (k = pi / (2h)), FP32: plan build and sweep kernel."""
+    out = {"workload": "ellipsoid4M at D = 16, 32, 64, k = pi / (2h), FP32"}
+    for d in (16, 32, 64):
+        inst = W.ellipsoid_4m(d)
+        xyz = torch.from_numpy(inst.xyz).cuda()
+        ids = torch.from_numpy(inst.ids).cuda()
+        q = torch.from_numpy(inst.q[:, 0].copy()).cuda()
+        row = {}
+        for layout in ("tiles", "csr"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=layout)
+            plan_ms = (time.perf_counter() - t0) * 1e3
+            n_pairs = plan.info()["n_pairs"]
+            plan.apply(q)
+            torch.cuda.synchronize()
+            plan.timing(True)
+            for _ in range(reps):
+                plan.apply(q)
+            torch.cuda.synchronize()
+            kern_ms, calls = plan.timing_read()
+            plan.timing(False)
+            kern_ms /= calls
+            row[layout] = {"plan_ms": round(plan_ms, 3), "sweep_ms": round(kern_ms, 4),
+                           "gpairs_s": round(n_pairs / kern_ms / 1e6, 2),
+                           "device_bytes": plan.info()["device_bytes"]}
+            plan.close()
+        row["n_pairs"] = n_pairs
+        out["D%d" % d] = row
+        log("ellipsoid D=%d: %d pairs; tiles %.1f Gpair/s (plan %.2f ms), csr %.1f Gpair/s (plan %.2f ms)" % (
+            d, n_pairs, row["tiles"]["gpairs_s"], row["tiles"]["plan_ms"], row["csr"]["gpairs_s"],
+            row["csr"]["plan_ms"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +247,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-mrhs", action="store_true", help="skip the multi-right-hand-side batch")
     ap.add_argument("--mrhs-only", action="store_true", help="only the multi-right-hand-side batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the reverse-pass and layout measurements on their own workloads")
     ap.add_argument("--layout", choices=["csr", "tiles"], default="csr",
                     help="source layout of the timed step and of the roofline kernel")
     ap.add_argument("--copy-probe", action="store_true",
@@ -324,6 +413,8 @@ def main():
         log("oracle %.1f s on %d threads; rel L2 f32 %.3e f64 %.3e" % (cpu_s, threads, errs["f32"], errs["f64"]))
     plan32.close()
     mrhs = None if args.no_mrhs else measure_mrhs(p2p, W, torch, max(3, args.apply_reps // 4), not args.no_cpu)
+    backward = None if args.no_extra else measure_backward(p2p, W, torch, max(3, args.apply_reps // 4))
+    layouts = None if args.no_extra else measure_layouts(p2p, W, torch, max(3, args.apply_reps // 4))
 
     value = n_pairs / step_s / 1e9
     line = {
@@ -349,6 +440,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "multi_rhs": mrhs,
+        "backward": backward,
+        "layouts": layouts,
     }
     print(json.dumps(line))
     return 0

@@ -47,10 +47,22 @@ __device__ T block_exclusive_scan(T v, T* lds, T* total) {
   return base + incl - v;
 }
 
+// lim (optional, device): only the first *lim + 1 entries are live; the rest are
+// zero and need not be read or written.
+__device__ __forceinline__ int64_t live(int64_t n, const int32_t* lim) {
+  return lim ? min(n, (int64_t)*lim + 1) : n;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ part) {
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ part,
+                                                     const int32_t* __restrict__ lim) {
   __shared__ T lds[kBlock / kWave];
   int64_t base = (int64_t)blockIdx.x * kScanTile;
+  n = live(n, lim);
+  if (base >= n) {
+    if (threadIdx.x == 0) part[blockIdx.x] = T(0);
+    return;
+  }
   T s = 0;
   for (int r = 0; r < kScanItems; ++r) {
     int64_t e = base + (int64_t)r * kBlock + threadIdx.x;
@@ -78,9 +90,11 @@ __global__ void __launch_bounds__(kBlock) k_scan_partials(T* __restrict__ part, 
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* __restrict__ in, int64_t n, const T* __restrict__ part,
-                                                    T* __restrict__ out) {
+                                                    T* __restrict__ out, const int32_t* __restrict__ lim) {
   // each thread owns kScanItems consecutive elements of the tile
   __shared__ T lds[kBlock / kWave];
+  n = live(n, lim);
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
   int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   T v[kScanItems];
   T s = 0;
@@ -106,106 +120,175 @@ __global__ void k_zero_one(T* p) {
 }
 
 template <typename T>
-static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s) {
+static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s,
+                       const int32_t* lim = nullptr) {
   if (n <= 0) {
     if (total) hipLaunchKernelGGL(k_zero_one<T>, dim3(1), dim3(kWave), 0, s, total);
     P2P_HIP(hipGetLastError());
     return P2P_OK;
   }
   unsigned g = grid_for(n, kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(g), dim3(kBlock), 0, s, in, n, part);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(g), dim3(kBlock), 0, s, in, n, part, lim);
   hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, total);
-  hipLaunchKernelGGL(k_scan_apply<T>, dim3(g), dim3(kBlock), 0, s, in, n, part, out);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(g), dim3(kBlock), 0, s, in, n, part, out, lim);
   P2P_HIP(hipGetLastError());
   return P2P_OK;
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (u64 key, i32 value), 8 bits per pass
+// Stable LSD radix sort of (key, i32 value), 8 bits per pass.  Per pass: digit
+// counts per tile, one scan over [digit][tile], then the scatter.  Keys are
+// narrowed to 32 bits by the first pass when the key bits in use allow it, and
+// the first pass makes the identity values itself.
 // ---------------------------------------------------------------------------
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kBlock * kRsItems;
+constexpr int kRsWaveItems = kRsItems * kWave;  // keys of one wavefront's part of a tile
 
-__global__ void __launch_bounds__(kBlock) k_rs_hist(const uint64_t* __restrict__ key, int64_t n, int shift,
+template <typename KI>
+__global__ void __launch_bounds__(kBlock) k_rs_hist(const KI* __restrict__ key, int64_t n, int shift,
                                                  uint32_t* __restrict__ hist, int g) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kRsTile;
-  for (int r = 0; r < kRsItems; ++r) {
-    int64_t e = base + (int64_t)r * kBlock + threadIdx.x;
-    if (e < n) atomicAdd(&h[(key[e] >> shift) & 255u], 1u);
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  KI k[kRsItems];
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {  // every load in flight before the first count
+    const int64_t e = base + (int64_t)r * kBlock + threadIdx.x;
+    k[r] = e < n ? key[e] : KI(0);
   }
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r)
+    if (base + (int64_t)r * kBlock + threadIdx.x < n) atomicAdd(&h[(uint32_t)(k[r] >> shift) & 255u], 1u);
   __syncthreads();
   hist[(int64_t)threadIdx.x * g + blockIdx.x] = h[threadIdx.x];
 }
 
-// Scatter one tile in input order.  Within a round of 256 elements the rank of
-// an element among equal digits comes from wave ballots (lanes below it with the
-// same digit) plus the counts of the waves before it; rounds are processed in
-// order, so equal digits keep their input order (stability).
-__global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin,
-                                                    uint64_t* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+// Scatter one tile.  Wavefront w ranks the w-th quarter of the tile on its own, in
+// input order: the rank of a key among equal digits is the count of that digit in
+// the wavefront's earlier rounds (an LDS counter per digit) plus the lanes below
+// it with the same digit (wave ballots).  Then the quarters are stacked in order
+// under the tile's offset for each digit, so equal digits keep their input order
+// (stability).  vin null: the values are the input positions.
+template <typename KI, typename KO>
+__global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                    KO* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
                                                     int shift, const uint32_t* __restrict__ offs, int g) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kBlock / kWave][256];
+  __shared__ uint32_t cnt[kBlock / kWave][256];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
-  run[tid] = offs[(int64_t)tid * g + blockIdx.x];
-  for (int w = 0; w < kBlock / kWave; ++w) wcnt[w][tid] = 0;
-  __syncthreads();
+  for (int d = lane; d < 256; d += kWave) cnt[wave][d] = 0;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)wave * kRsWaveItems;
+  // every load of the wavefront's quarter in flight before the ranking
+  KI k[kRsItems];
+  int32_t v[kRsItems];
+#pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
-    int64_t e = base + (int64_t)r * kBlock + tid;
-    bool valid = e < n;
-    uint64_t k = valid ? kin[e] : 0ull;
-    uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const int64_t e = base + (int64_t)r * kWave + lane;
+    k[r] = e < n ? kin[e] : KI(0);
+    v[r] = e < n ? (vin ? vin[e] : (int32_t)e) : 0;
+  }
+  // LDS accesses of one wavefront take effect in program order, so a round's
+  // counter reads see the previous round's writes without a barrier
+  uint32_t pos[kRsItems];
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t e = base + (int64_t)r * kWave + lane;
+    const bool valid = e < n;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
+#pragma unroll
     for (int b = 0; b < 8; ++b) {
-      uint64_t bb = __ballot((d >> b) & 1u);
+      const uint64_t bb = __ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    uint32_t rank = __popcll(peers & below);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = k;
-      vout[pos] = vin[e];
+    const uint32_t rank = __popcll(peers & below);
+    const uint32_t before = cnt[wave][d];
+    pos[r] = before + rank;
+    if (valid && rank == 0) cnt[wave][d] = before + __popcll(peers);
+  }
+  __syncthreads();
+  // thread tid: digit tid; the quarters' start slots, in order
+  uint32_t run = offs[(int64_t)tid * g + blockIdx.x];
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    const uint32_t c = cnt[w][tid];
+    cnt[w][tid] = run;
+    run += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    const int64_t e = base + (int64_t)r * kWave + lane;
+    if (e < n) {
+      const uint32_t at = cnt[wave][(uint32_t)(k[r] >> shift) & 255u] + pos[r];
+      kout[at] = (KO)k[r];
+      vout[at] = v[r];
     }
-    __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < kBlock / kWave; ++w) {
-      add += wcnt[w][tid];
-      wcnt[w][tid] = 0;
-    }
-    run[tid] += add;
-    __syncthreads();
   }
 }
 
-// Sorts (k0, v0) by the low `bits` bits of the key.  Result is in (k0, v0) or
-// (k1, v1); *in_second tells which.  hist: 256 * grid entries, part: scan workspace.
-static p2p_status radix_sort(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n, int bits,
-                             uint32_t* hist, uint32_t* part, bool* in_second, hipStream_t s) {
-  *in_second = false;
-  if (n <= 1 || bits <= 0) return P2P_OK;
-  int g = (int)grid_for(n, kRsTile);
-  uint64_t* ka = k0;
-  int32_t* va = v0;
-  uint64_t* kb = k1;
-  int32_t* vb = v1;
-  for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(g), dim3(kBlock), 0, s, ka, n, shift, hist, g);
+__global__ void __launch_bounds__(kBlock) k_iota(int32_t* __restrict__ v, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e < n) v[e] = (int32_t)e;
+}
+
+// Sorts the keys k0[0..n) by their low `bits` bits; the stable order of the
+// positions lands in vals.  Workspace: kx (n u64), vx (n i32).  Returns in *sorted
+// the sorted keys: 32-bit (in kx's storage) when bits <= 32, else 64-bit (k0 or kx).
+struct SortedKeys {
+  const uint32_t* k32;
+  const uint64_t* k64;
+};
+
+static p2p_status radix_sort(uint64_t* k0, int32_t* vals, uint64_t* kx, int32_t* vx, int64_t n, int bits,
+                             uint32_t* hist, uint32_t* part, SortedKeys* sorted, hipStream_t s) {
+  const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
+  const bool narrow = bits <= 32;
+  sorted->k32 = nullptr;
+  sorted->k64 = k0;
+  if (n <= 0) return P2P_OK;
+  const int g = (int)grid_for(n, kRsTile);
+  if (passes == 0) {  // every key equal: the identity order
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, vals, n);
+    P2P_HIP(hipGetLastError());
+    return P2P_OK;
+  }
+  uint32_t* a32 = reinterpret_cast<uint32_t*>(kx);
+  uint32_t* b32 = a32 + n;
+  const uint64_t* cur64 = k0;
+  const uint32_t* cur32 = nullptr;
+  const int32_t* vcur = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    // the last pass writes vals, the ones before alternate backwards from it
+    int32_t* vout = ((passes - 1 - p) % 2 == 0) ? vals : vx;
+    if (cur32)
+      hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(g), dim3(kBlock), 0, s, cur32, n, shift, hist, g);
+    else
+      hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(g), dim3(kBlock), 0, s, cur64, n, shift, hist, g);
     p2p_status st = scan<uint32_t>(hist, hist, (int64_t)256 * g, part, nullptr, s);
     if (st != P2P_OK) return st;
-    hipLaunchKernelGGL(k_rs_scatter, dim3(g), dim3(kBlock), 0, s, ka, va, kb, vb, n, shift, hist, g);
+    if (narrow) {
+      uint32_t* kout = (p % 2 == 0) ? a32 : b32;
+      if (cur32)
+        hipLaunchKernelGGL((k_rs_scatter<uint32_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur32, vcur, kout, vout, n,
+                           shift, hist, g);
+      else
+        hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
+                           shift, hist, g);
+      cur32 = kout;
+    } else {
+      uint64_t* kout = (p % 2 == 0) ? kx : k0;
+      hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint64_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
+                         shift, hist, g);
+      cur64 = kout;
+    }
     P2P_HIP(hipGetLastError());
-    std::swap(ka, kb);
-    std::swap(va, vb);
-    *in_second = !*in_second;
+    vcur = vout;
   }
+  sorted->k32 = cur32;
+  sorted->k64 = cur32 ? nullptr : cur64;
   return P2P_OK;
 }
 
@@ -323,20 +406,18 @@ __global__ void __launch_bounds__(kBlock) k_init(uint32_t* __restrict__ zero, in
   }
 }
 
-// Morton keys, identity values, validation, and the bit width and range of the
-// ids (grid-stride; one partial row per workgroup).
-__global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ xyz, const int32_t* __restrict__ ids,
-                                              int64_t n, uint64_t* __restrict__ key, int32_t* __restrict__ idx,
-                                              Partial* __restrict__ part) {
+// Morton keys, validation of the ids, and their bit width and range (grid-stride;
+// one partial row per workgroup).  The coordinates are checked later, where the
+// geometry pass reads them.
+__global__ void __launch_bounds__(kBlock) k_keys(const int32_t* __restrict__ ids, int64_t n,
+                                              uint64_t* __restrict__ key, Partial* __restrict__ part) {
   __shared__ uint32_t lds[kWavesPerBlockPlan];
   uint32_t bad = 0, orv = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   const uint32_t lim = 1u << kIdBits;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     const int32_t a = ids[3 * i], b = ids[3 * i + 1], c = ids[3 * i + 2];
     const bool bad_id = ((uint32_t)a >= lim) | ((uint32_t)b >= lim) | ((uint32_t)c >= lim);
-    const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-    const bool bad_x = !(isfinite(x) && isfinite(y) && isfinite(z));
-    bad |= (bad_id ? 1u : 0u) | (bad_x ? 2u : 0u);
+    bad |= bad_id ? 1u : 0u;
     const uint32_t u[3] = {(uint32_t)a & kIdMask, (uint32_t)b & kIdMask, (uint32_t)c & kIdMask};
     orv |= u[0] | u[1] | u[2];
     for (int d = 0; d < 3; ++d) {
@@ -344,7 +425,6 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ xyz,
       hi[d] = max(hi[d], u[d]);
     }
     key[i] = morton3(u[0], u[1], u[2]);
-    idx[i] = (int32_t)i;
   }
   auto vor = [](uint32_t x, uint32_t y) { return x | y; };
   auto vmax = [](uint32_t x, uint32_t y) { return x > y ? x : y; };
@@ -365,7 +445,8 @@ __global__ void __launch_bounds__(kBlock) k_keys(const double* __restrict__ xyz,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_box_flags(const uint64_t* __restrict__ key, int64_t n,
+template <typename K>
+__global__ void __launch_bounds__(kBlock) k_box_flags(const K* __restrict__ key, int64_t n,
                                                    int32_t* __restrict__ flag) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p < n) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
@@ -383,14 +464,15 @@ struct CellGrid {
 };
 
 // excl holds the exclusive scan of the run-start flags: the box of a run start p is excl[p].
-__global__ void __launch_bounds__(kBlock) k_box_write(const uint64_t* __restrict__ key, int64_t n,
+template <typename K>
+__global__ void __launch_bounds__(kBlock) k_box_write(const K* __restrict__ key, int64_t n,
                                                    const int32_t* __restrict__ excl, uint64_t* __restrict__ box_key,
                                                    int32_t* __restrict__ box_start,
                                                    const DevStatus* __restrict__ status, CellGrid grid) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
   const uint64_t k = key[p];
-  if (p == 0 || k != key[p - 1]) {
+  if (p == 0 || k != (uint64_t)key[p - 1]) {
     const int32_t b = excl[p];
     box_key[b] = k;
     box_start[b] = (int32_t)p;
@@ -410,6 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
   const int lane = threadIdx.x & (kWave - 1);
   const int32_t nb = status->nbox;
   uint32_t tmax = 0;
+  bool bad_x = false;
   double amax = 0.0;
   for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
        T += gridDim.x * kWavesPerBlockPlan) {
@@ -424,6 +507,7 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
       const int64_t i = perm[p];
       for (int d = 0; d < 3; ++d) {
         const double v = xyz[3 * i + d];
+        bad_x |= !isfinite(v);
         sx[d * n + p] = v;
         lo[d] = fmin(lo[d], v);
         hi[d] = fmax(hi[d], v);
@@ -444,9 +528,11 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
   }
   tmax = block_combine63(tmax, ldsu, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
   amax = block_combine63(amax, ldsd, [](double x, double y) { return fmax(x, y); });
+  const uint32_t bx = block_combine63(wave_or63(bad_x ? 2u : 0u), ldsu, [](uint32_t x, uint32_t y) { return x | y; });
   if (threadIdx.x == 0) {
     part[blockIdx.x].tmax = tmax;
     part[blockIdx.x].maxabs = amax;
+    part[blockIdx.x].bad |= bx;
   }
 }
 
@@ -604,13 +690,12 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
 // bucketed on a log scale (8 buckets per octave), Morton order inside a bucket.
 __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict__ box_start,
                                                    const int32_t* __restrict__ src, int32_t nb,
-                                                   uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
+                                                   uint64_t* __restrict__ key) {
   const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (T >= nb) return;
   const double c = (double)(box_start[T + 1] - box_start[T]) * (double)src[T];
   const int b = (int)fmin(255.0, floor(log2(c + 1.0) * 8.0));
   key[T] = (uint64_t)(255 - b);
-  idx[T] = (int32_t)T;
 }
 
 // Zero-distance pairs (self pairs included), FP64 coordinates.
@@ -819,8 +904,8 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   }
 
   // ---- 1. Morton keys and validation (first readback)
-  hipLaunchKernelGGL(k_keys, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n))), dim3(kBlock), 0, s, xyz, ids,
-                     n, k0, P->perm, part);
+  hipLaunchKernelGGL(k_keys, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n))), dim3(kBlock), 0, s, ids, n,
+                     k0, part);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
   DevStatus hs;
@@ -850,18 +935,23 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
 
   // ---- 2. stable sort of the points by key, over the key bits in use
   const int bits = 3 * bit_length(hs.st[ST_ID_OR]);
-  bool second = false;
-  rc = radix_sort(k0, P->perm, k1, v1, n, bits, hist, partu, &second, s);
+  SortedKeys sk;
+  rc = radix_sort(k0, P->perm, k1, v1, n, bits, hist, partu, &sk, s);
   if (rc != P2P_OK) return rc;
-  const uint64_t* skey = second ? k1 : k0;
-  if (second) P2P_HIP(hipMemcpyAsync(P->perm, v1, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
 
   // ---- 3. box table: runs of equal keys
-  hipLaunchKernelGGL(k_box_flags, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag);
+  if (sk.k32)
+    hipLaunchKernelGGL(k_box_flags<uint32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k32, n, flag);
+  else
+    hipLaunchKernelGGL(k_box_flags<uint64_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k64, n, flag);
   rc = scan<int32_t>(flag, flag, n, part32, &status->nbox, s);
   if (rc != P2P_OK) return rc;
-  hipLaunchKernelGGL(k_box_write, dim3(grid_for(n)), dim3(kBlock), 0, s, skey, n, flag, P->box_key, P->box_start,
-                     status, grid);
+  if (sk.k32)
+    hipLaunchKernelGGL(k_box_write<uint32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k32, n, flag, P->box_key,
+                       P->box_start, status, grid);
+  else
+    hipLaunchKernelGGL(k_box_write<uint64_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k64, n, flag, P->box_key,
+                       P->box_start, status, grid);
   const unsigned gs = (unsigned)std::min<int64_t>(kGridStride, grid_for(n, kWavesPerBlockPlan));
   hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, status, P->sx64, bb,
                      part);
@@ -873,14 +963,15 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
                      nullptr, nullptr, part);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
-  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, &status->nnz, s);
+  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, &status->nnz, s, &status->nbox);
   if (rc != P2P_OK) return rc;
-  rc = scan<int32_t>(src, P->tile_start, n + 1, part32, nullptr, s);
+  rc = scan<int32_t>(src, P->tile_start, n + 1, part32, nullptr, s, &status->nbox);
   if (rc != P2P_OK) return rc;
 
   // second readback: sizes of the lists and the geometry bounds
   rc = read_status(status, &hs, s);
   if (rc != P2P_OK) return rc;
+  if (hs.st[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
   const int32_t B = hs.nbox;
   P->B = B;
   P->nnz = hs.nnz;
@@ -936,11 +1027,10 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
   }
   // processing order: most pair slots first (one 8-bit radix pass, stable)
-  hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_start, src, B, k0, P->work);
+  hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_start, src, B, k0);
   P2P_HIP(hipGetLastError());
-  rc = radix_sort(k0, P->work, k1, v1, B, 8, hist, partu, &second, s);
+  rc = radix_sort(k0, P->work, k1, v1, B, 8, hist, partu, &sk, s);
   if (rc != P2P_OK) return rc;
-  if (second) P2P_HIP(hipMemcpyAsync(P->work, v1, sizeof(int32_t) * B, hipMemcpyDeviceToDevice, s));
   P2P_HIP(hipGetLastError());
   P2P_HIP(hipStreamSynchronize(s));
   return P2P_OK;
