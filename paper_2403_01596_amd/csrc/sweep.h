@@ -118,6 +118,7 @@ struct SweepGeom {
   int64_t n;
   const int32_t* perm;
   typename Tr::real kparam;      // F32: turns per quantum; F64: k
+  typename Tr::coord far;        // x offset of padding entries: farther than any near pair
   bool may_coincide;             // points of distinct boxes may coincide: mask every chunk
 };
 
@@ -139,10 +140,12 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
     G.tx = P->tile_x32;
     G.sx = P->sx32;
     G.kparam = (float)(P->k * std::ldexp(1.0, P->qexp) / (2.0 * M_PI));
+    G.far = 1 << 30;  // near-pair differences stay below 2^30 quanta
   } else {
     G.tx = P->tile_x64;
     G.sx = P->sx64;
     G.kparam = P->k;
+    G.far = 2.0 * P->max_sep + 1.0;  // near-pair differences stay below max_sep
   }
   return G;
 }
@@ -181,6 +184,63 @@ struct SweepLds {
   int32_t idx[CSR ? kWave * Tr::K : 1];
 };
 
+// Which chunks of a group take the zero-distance mask: every chunk, the first
+// only (the group holds the box's own points, at most 64, in its first chunk), or
+// none.  Three straight-line forms of the target loop, chosen per group: a branch
+// per chunk between a masked and a plain form made the compiler copy the
+// accumulators at every join.
+enum SweepMask { kMaskAll, kMaskFirst, kMaskNone };
+
+// All targets of the block [tb, te) against the group's chunks in registers.
+template <class Tr, class Op, bool HELM, int MODE, class LdsT>
+__device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& op, LdsT& L,
+                                              const typename Tr::coord (&X)[Tr::K],
+                                              const typename Tr::coord (&Y)[Tr::K],
+                                              const typename Tr::coord (&Z)[Tr::K],
+                                              const typename Tr::real (&P)[Tr::K][Op::NP > 0 ? Op::NP : 1], int nch,
+                                              int32_t tb, int32_t te, bool first_group) {
+  using real = typename Tr::real;
+  using coord = typename Tr::coord;
+  constexpr int K = Tr::K;
+  constexpr int NT = Op::NT, NA = Op::NA;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t n = G.n;
+  // target coordinates are fetched one target ahead
+  coord nx = ld_uniform(G.sx + tb), ny = ld_uniform(G.sx + n + tb), nz = ld_uniform(G.sx + 2 * n + tb);
+  for (int32_t t = tb; t < te; ++t) {
+    const coord px = nx, py = ny, pz = nz;
+    if (t + 1 < te) {
+      nx = ld_uniform(G.sx + t + 1);
+      ny = ld_uniform(G.sx + n + t + 1);
+      nz = ld_uniform(G.sx + 2 * n + t + 1);
+    }
+    real tp[NT > 0 ? NT : 1];
+    op.load_tgt(t, tp);
+    real acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = real(0);
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (c < nch) {
+        // c is a constant in each unrolled copy, so this choice costs no branch
+        const bool masked = MODE == kMaskAll || (MODE == kMaskFirst && c == 0);
+        if (masked) {
+          const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+          op.template pair<HELM>(g, P[c], tp, acc);
+        } else {
+          const typename Tr::Geo g = Tr::template geo<HELM, false>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+          op.template pair<HELM>(g, P[c], tp, acc);
+        }
+      }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = wave_sum63(acc[a]);
+    if (lane == kWave - 1) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
+    }
+  }
+}
+
 // The sweep.  Op supplies:
 //   NP, NT, NA            payload reals per source, per target, accumulators
 //   load_src(p, pay)      payload of the source at sorted position p
@@ -192,7 +252,7 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
   using real = typename Tr::real;
   using coord = typename Tr::coord;
   constexpr int K = Tr::K;
-  constexpr int NP = Op::NP, NT = Op::NT, NA = Op::NA;
+  constexpr int NP = Op::NP, NA = Op::NA;
   const int lane = threadIdx.x & (kWave - 1);
   const int32_t w = uniform((int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
   if (w >= G.nb) return;
@@ -219,8 +279,9 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
       real P[K][NP > 0 ? NP : 1];
 #pragma unroll
       for (int c = 0; c < K; ++c) {
-        // Entries past the end repeat the group's first source with a zero
-        // payload: a finite term that adds exactly zero.
+        // Entries past the end take the group's first source moved G.far along x,
+        // with a zero payload: a finite term (the distance is never zero) that adds
+        // exactly zero.
         const int32_t e = sg + c * kWave + lane;
         const bool ok = e < s1;
         X[c] = Y[c] = Z[c] = coord(0);
@@ -241,44 +302,26 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
             Z[c] = G.tx[2 * tl + e2];
           }
           if (ok) op.load_src(p, P[c]);
+          if (!ok) {
+            if constexpr (std::is_same<coord, int32_t>::value)
+              X[c] = (int32_t)((uint32_t)X[c] + (uint32_t)G.far);  // modulo 2^32, like every difference
+            else
+              X[c] += G.far;
+          }
         }
       }
       const bool first_group = sg == s0;
-      // target coordinates are fetched one target ahead
-      coord nx = ld_uniform(G.sx + tb), ny = ld_uniform(G.sx + n + tb), nz = ld_uniform(G.sx + 2 * n + tb);
-      for (int32_t t = tb; t < te; ++t) {
-        const coord px = nx, py = ny, pz = nz;
-        if (t + 1 < te) {
-          nx = ld_uniform(G.sx + t + 1);
-          ny = ld_uniform(G.sx + n + t + 1);
-          nz = ld_uniform(G.sx + 2 * n + t + 1);
-        }
-        real tp[NT > 0 ? NT : 1];
-        op.load_tgt(t, tp);
-        real acc[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) acc[a] = real(0);
-#pragma unroll
-        for (int c = 0; c < K; ++c)
-          if (c < nch) {
-            // Only a chunk holding the box's own points (listed first), the padded
-            // tail chunk, or any chunk when boxes overlap, can meet r = 0.
-            const int32_t rel = sg - s0 + c * kWave;
-            if (G.may_coincide || rel < t1 - t0 || rel + kWave > s1 - s0) {
-              const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
-              op.template pair<HELM>(g, P[c], tp, acc);
-            } else {
-              const typename Tr::Geo g = Tr::template geo<HELM, false>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
-              op.template pair<HELM>(g, P[c], tp, acc);
-            }
-          }
-#pragma unroll
-        for (int a = 0; a < NA; ++a) acc[a] = wave_sum63(acc[a]);
-        if (lane == kWave - 1) {
-#pragma unroll
-          for (int a = 0; a < NA; ++a) L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
-        }
-      }
+      // A zero distance can only occur among the box's own points, entries
+      // [s0, s0 + n_T), unless points of distinct boxes may coincide.  Padding
+      // entries sit far away.  The first-chunk form needs all own points in the
+      // first chunk of the first group.
+      const bool own_here = sg < s0 + (t1 - t0);
+      if (G.may_coincide || (own_here && !(first_group && t1 - t0 <= kWave)))
+        sweep_targets<Tr, Op, HELM, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
+      else if (first_group)
+        sweep_targets<Tr, Op, HELM, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
+      else
+        sweep_targets<Tr, Op, HELM, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
     }
     wave_lds_sync();
