@@ -5,9 +5,10 @@
 Workload: 2M points uniform on the unit sphere, leaf boxes sized for ~32 points
 per non-empty box, k = 2 pi * 64, complex64 strengths ~ N(0,1), one right-hand
 side (seeded, synthetic).  One step is one pass of the whole path on that input,
-already resident in HBM: leaf-box ids from the positions, the plan build (Morton
-keys, sort, box table, neighbour lists; replicated source lists for the tiles
-layout), the FP32 apply y = A_near q, and the plan's release.  The step uses the
+already resident in HBM: the plan build with the leaf-box ids computed from the
+positions inside it (Morton keys, sort, box table, neighbour lists; replicated
+source lists for the tiles layout), the FP32 apply y = A_near q, and the plan's
+release.  The step uses the
 non-redundant CSR layout unless --layout tiles is given; the other layout is
 timed beside it.
 
@@ -303,8 +304,7 @@ def main():
         return 0
 
     def step():
-        ids = p2p.box_ids(xyz, origin, inst.h)
-        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
+        plan = p2p.Plan.from_grid(xyz, origin, inst.h, inst.k, dtype=torch.complex64, layout=args.layout)
         y = plan.apply(q32)
         plan.close()
         return y
@@ -321,23 +321,26 @@ def main():
     log("step %.3f ms" % (step_s * 1e3))
 
     # ---- where the step's time goes: each phase bracketed by synchronisations
-    phases = {"box_ids": 0.0, "plan_create": 0.0, "apply": 0.0, "release": 0.0}
+    phases = {"plan_create": 0.0, "apply": 0.0, "release": 0.0}
     for _ in range(args.steps):
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ids_b = p2p.box_ids(xyz, origin, inst.h)
-        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pl = p2p.Plan(xyz, ids_b, inst.k, dtype=torch.complex64, layout=args.layout)
+        pl = p2p.Plan.from_grid(xyz, origin, inst.h, inst.k, dtype=torch.complex64, layout=args.layout)
         t2 = time.perf_counter()
         pl.apply(q32)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         pl.close()
         t4 = time.perf_counter()
-        for key, dt in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+        for key, dt in zip(phases, (t2 - t1, t3 - t2, t4 - t3)):
             phases[key] += dt * 1e3 / args.steps
     log("phases (ms): " + ", ".join("%s %.3f" % kv for kv in phases.items()))
+    # the box ids on their own (p2p_box_ids, one synchronisation), for comparison
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p2p.box_ids(xyz, origin, inst.h)
+    box_ids_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # ---- pieces of the step, on resident plans
     ids = p2p.box_ids(xyz, origin, inst.h)
@@ -427,7 +430,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": inst.name, "n_points": inst.n, "k": inst.k, "leaf_h": inst.h,
                    "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": args.layout,
-                   "step": "box ids + plan build + FP32 apply + release"},
+                   "step": "plan build with the leaf-box ids from (origin, h) + FP32 apply + release"},
         "rel_err": errs or None,
         "n_pairs": n_pairs,
         "apply": {"f32_%s_gpairs_s" % args.layout: round(n_pairs / apply32_ms / 1e6, 2),
@@ -439,6 +442,7 @@ def main():
                                "f64_" + args.layout: round(sweep64_ms, 4)}},
         "plan_ms": round(plan_s * 1e3, 3),
         "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "box_ids_call_ms": round(box_ids_ms, 4),
         "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -110,6 +110,15 @@ p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, doubl
 p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n, double k, const p2p_opts* opts,
                            void* stream, p2p_plan* out);
 
+/* The same plan with the ids computed inside the build from the positions and a
+ * uniform leaf grid: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h), evaluated
+ * exactly as p2p_box_ids does (paper section 3.1), without writing or reading an
+ * id array and without p2p_box_ids' own synchronisation.  origin: host double[3];
+ * h finite and > 0.  Returns P2P_ERR_RANGE if a coordinate is not finite or an id
+ * falls outside [0, 2^21).  Otherwise as p2p_plan_create. */
+p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* origin, double h, double k,
+                                const p2p_opts* opts, void* stream, p2p_plan* out);
+
 /* Plan statistics (paper section 3.2: t, the largest box occupancy; section 3.4.1:
  * D, the mean number of points per box).  n_pairs and n_zero_pairs are counted on
  * the device the first time they are asked for (synchronously). */

@@ -59,6 +59,7 @@ def lib():
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.p2p_box_ids.argtypes = [P, i64, P, f64, P, P]
     L.p2p_plan_create.argtypes = [P, P, i64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
+    L.p2p_plan_create_grid.argtypes = [P, i64, P, f64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_info.argtypes = [P, ctypes.POINTER(_Info)]
     L.p2p_plan_export.argtypes = [P, P, P, P, P, P]
     L.p2p_apply.argtypes = [P, P, P, i32, ctypes.c_int, P]
@@ -76,7 +77,7 @@ def lib():
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
-    for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
+    for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
                  "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
                  "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
                  "p2p_batch_timing_read", "p2p_batch_destroy"):
@@ -124,8 +125,9 @@ class Plan:
         if dtype not in (torch.complex64, torch.complex128):
             raise TypeError("dtype must be complex64 or complex128")
         xyz = _cuda(xyz, torch.float64, "xyz")
-        ids = _cuda(ids, torch.int32, "ids")
-        if xyz.dim() != 2 or xyz.shape[1] != 3 or ids.shape != xyz.shape:
+        if ids is not None:
+            ids = _cuda(ids, torch.int32, "ids")
+        if xyz.dim() != 2 or xyz.shape[1] != 3 or (ids is not None and ids.shape != xyz.shape):
             raise ValueError("xyz and ids must both be [n, 3]")
         self.dtype = dtype
         self.layout = layout
@@ -135,9 +137,23 @@ class Plan:
         self.device = xyz.device
         opts = _Opts(P2P_C64 if dtype == torch.complex64 else P2P_C128, LAYOUTS[layout], self.max_rhs, 0)
         h = ctypes.c_void_p()
-        _check(lib().p2p_plan_create(_ptr(xyz), _ptr(ids), self.n, self.k, ctypes.byref(opts), _stream(),
-                                     ctypes.byref(h)))
+        if ids is None:  # leaf grid given by from_grid
+            org = (ctypes.c_double * 3)(*self._grid[0])
+            _check(lib().p2p_plan_create_grid(_ptr(xyz), self.n, org, float(self._grid[1]), self.k,
+                                              ctypes.byref(opts), _stream(), ctypes.byref(h)))
+        else:
+            _check(lib().p2p_plan_create(_ptr(xyz), _ptr(ids), self.n, self.k, ctypes.byref(opts), _stream(),
+                                         ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def from_grid(cls, xyz: torch.Tensor, origin, h: float, k: float, dtype=torch.complex64, layout: str = "tiles",
+                  max_rhs: int = 1) -> "Plan":
+        """The plan with leaf-box ids floor((xyz - origin) / h) computed inside the build."""
+        self = cls.__new__(cls)
+        self._grid = ([float(v) for v in origin], float(h))
+        cls.__init__(self, xyz, None, k, dtype=dtype, layout=layout, max_rhs=max_rhs)
+        return self
 
     @property
     def handle(self):

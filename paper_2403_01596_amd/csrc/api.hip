@@ -104,12 +104,15 @@ p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, doubl
   return box_ids(xyz, n, origin, h, box_ijk, (hipStream_t)stream);
 }
 
-p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n, double k, const p2p_opts* opts,
-                           void* stream, p2p_plan* out) {
+namespace {
+
+// Common to both create calls: ids from box_ijk, or (box_ijk null) from gspec.
+p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::GridSpec* gspec, int64_t n, double k,
+                       const p2p_opts* opts, void* stream, p2p_plan* out) {
   if (!out) return fail(P2P_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
-  if (n > 0 && (!xyz || !box_ijk)) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
+  if (n > 0 && (!xyz || (!box_ijk && !gspec))) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
   // neighbour-list entries (at most 27 n) are 32-bit offsets
   if (n > (int64_t)(0x7fffffff / 27)) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
   if (!std::isfinite(k) || k < 0) return fail(P2P_ERR_RANGE, "k must be finite and >= 0");
@@ -138,7 +141,7 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
     delete P;
     return fail(P2P_ERR_NOMEM, "host allocation failed");
   }
-  p2p_status rc = build_plan(P, xyz, box_ijk, (hipStream_t)stream);
+  p2p_status rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, (hipStream_t)stream);
   if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin)
     rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
   if (rc != P2P_OK) {
@@ -149,6 +152,36 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
   }
   *out = P;
   return P2P_OK;
+}
+
+}  // namespace
+
+p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n, double k, const p2p_opts* opts,
+                           void* stream, p2p_plan* out) {
+  if (n > 0 && !box_ijk) {
+    if (out) *out = nullptr;
+    return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
+  }
+  return create_plan(xyz, box_ijk, nullptr, n, k, opts, stream, out);
+}
+
+p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* origin, double h, double k,
+                                const p2p_opts* opts, void* stream, p2p_plan* out) {
+  if (!origin) {
+    if (out) *out = nullptr;
+    return fail(P2P_ERR_ARG, "origin is NULL");
+  }
+  if (!(h > 0.0) || !std::isfinite(h)) {
+    if (out) *out = nullptr;
+    return fail(P2P_ERR_RANGE, "h must be finite and > 0");
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) {
+      if (out) *out = nullptr;
+      return fail(P2P_ERR_RANGE, "origin must be finite");
+    }
+  const p2p::GridSpec g{{origin[0], origin[1], origin[2]}, h};
+  return create_plan(xyz, nullptr, &g, n, k, opts, stream, out);
 }
 
 p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {

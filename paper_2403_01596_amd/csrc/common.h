@@ -100,7 +100,14 @@ struct StagingLock {
 StagingLock staging(size_t bytes);
 
 // plan build (plan.hip)
-p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipStream_t s);
+// Leaf grid of the positions: id = floor((x - o) / h) per axis.
+struct GridSpec {
+  double o[3];
+  double h;
+};
+
+// ids null: computed from xyz with gspec.
+p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, const GridSpec* gspec, hipStream_t s);
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s);
 p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids, hipStream_t s);
 

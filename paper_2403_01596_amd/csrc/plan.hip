@@ -409,13 +409,33 @@ __global__ void __launch_bounds__(kBlock) k_init(uint32_t* __restrict__ zero, in
 // Morton keys, validation of the ids, and their bit width and range (grid-stride;
 // one partial row per workgroup).  The coordinates are checked later, where the
 // geometry pass reads them.
-__global__ void __launch_bounds__(kBlock) k_keys(const int32_t* __restrict__ ids, int64_t n,
-                                              uint64_t* __restrict__ key, Partial* __restrict__ part) {
+// Leaf-box id of one coordinate: floor((x - o) / h) in FP64 (correctly rounded
+// subtraction and division), -1 when it is not an id (out of range or not finite).
+__device__ __forceinline__ int32_t grid_id(double x, double o, double h) {
+  const double v = floor((x - o) / h);
+  return (v >= 0.0 && v < (double)(1 << kIdBits)) ? (int32_t)v : -1;
+}
+
+// GRID: the ids are computed from the positions, the origin and the box size
+// (ids unused); else read from ids.
+template <bool GRID>
+__global__ void __launch_bounds__(kBlock) k_keys(const int32_t* __restrict__ ids, const double* __restrict__ xyz,
+                                              GridSpec gs, int64_t n, uint64_t* __restrict__ key,
+                                              Partial* __restrict__ part) {
   __shared__ uint32_t lds[kWavesPerBlockPlan];
   uint32_t bad = 0, orv = 0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   const uint32_t lim = 1u << kIdBits;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const int32_t a = ids[3 * i], b = ids[3 * i + 1], c = ids[3 * i + 2];
+    int32_t a, b, c;
+    if (GRID) {
+      a = grid_id(xyz[3 * i], gs.o[0], gs.h);
+      b = grid_id(xyz[3 * i + 1], gs.o[1], gs.h);
+      c = grid_id(xyz[3 * i + 2], gs.o[2], gs.h);
+    } else {
+      a = ids[3 * i];
+      b = ids[3 * i + 1];
+      c = ids[3 * i + 2];
+    }
     const bool bad_id = ((uint32_t)a >= lim) | ((uint32_t)b >= lim) | ((uint32_t)c >= lim);
     bad |= bad_id ? 1u : 0u;
     const uint32_t u[3] = {(uint32_t)a & kIdMask, (uint32_t)b & kIdMask, (uint32_t)c & kIdMask};
@@ -828,7 +848,7 @@ p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h,
   return P2P_OK;
 }
 
-p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipStream_t s) {
+p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, const GridSpec* gspec, hipStream_t s) {
   const int64_t n = P->n;
   const bool f64 = P->precision == P2P_C128;
   const bool tiles = P->layout == P2P_LAYOUT_TILES;
@@ -904,14 +924,20 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, hipS
   }
 
   // ---- 1. Morton keys and validation (first readback)
-  hipLaunchKernelGGL(k_keys, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n))), dim3(kBlock), 0, s, ids, n,
-                     k0, part);
+  const unsigned gk = (unsigned)std::min<int64_t>(kGridStride, grid_for(n));
+  if (gspec)
+    hipLaunchKernelGGL(k_keys<true>, dim3(gk), dim3(kBlock), 0, s, nullptr, xyz, *gspec, n, k0, part);
+  else
+    hipLaunchKernelGGL(k_keys<false>, dim3(gk), dim3(kBlock), 0, s, ids, nullptr, GridSpec{{0, 0, 0}, 1.0}, n, k0,
+                       part);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
   DevStatus hs;
   rc = read_status(status, &hs, s);
   if (rc != P2P_OK) return rc;
-  if (hs.st[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a box id falls outside [0, 2^21)");
+  if (hs.st[ST_BAD_ID])
+    return fail(P2P_ERR_RANGE, gspec ? "a coordinate is not finite or its box id falls outside [0, 2^21)"
+                                     : "a box id falls outside [0, 2^21)");
   if (hs.st[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
 
   // dense cell table when the occupied id range is small enough

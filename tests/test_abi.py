@@ -64,6 +64,17 @@ def test_argument_errors_before_device_work():
     assert L.p2p_box_ids(None, -1, origin, 1.0, None, None) == 1
     assert L.p2p_box_ids(dummy, 5, origin, 0.0, dummy, None) == 2
     assert L.p2p_box_ids(dummy, 5, None, 1.0, dummy, None) == 1
+    # the plan from a leaf grid
+    assert L.p2p_plan_create_grid(dummy, 5, None, 1.0, 1.0, None, None, ctypes.byref(out)) == 1
+    assert L.p2p_plan_create_grid(dummy, 5, origin, 0.0, 1.0, None, None, ctypes.byref(out)) == 2
+    assert L.p2p_plan_create_grid(dummy, 5, origin, float("nan"), 1.0, None, None, ctypes.byref(out)) == 2
+    assert L.p2p_plan_create_grid(dummy, 5, (ctypes.c_double * 3)(0, float("inf"), 0), 1.0, 1.0, None, None,
+                                  ctypes.byref(out)) == 2
+    assert L.p2p_plan_create_grid(dummy, -1, origin, 1.0, 1.0, None, None, ctypes.byref(out)) == 1
+    assert L.p2p_plan_create_grid(None, 5, origin, 1.0, 1.0, None, None, ctypes.byref(out)) == 1
+    assert L.p2p_plan_create_grid(dummy, 5, origin, 1.0, -2.0, None, None, ctypes.byref(out)) == 2
+    assert L.p2p_plan_create_grid(dummy, 5, origin, 1.0, 1.0, None, None, None) == 1
+    assert out.value is None
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

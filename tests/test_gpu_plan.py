@@ -87,3 +87,41 @@ def test_errors_from_device_validation():
     with pytest.raises(p2p.P2PError) as e:
         P.apply(torch.ones((100, 2), dtype=torch.complex64, device="cuda"))
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("dtype,layout", [(torch.complex64, "csr"), (torch.complex128, "tiles")])
+def test_plan_from_grid_equals_plan_from_ids(dtype, layout):
+    """p2p_plan_create_grid computes the ids inside the build: the same tables as
+    p2p_box_ids + p2p_plan_create, and bitwise the same products."""
+    inst = W.sphere(60000, 32, 2 * np.pi * 12, seed=21)
+    xyz = dev(inst.xyz, torch.float64)
+    ids = p2p.box_ids(xyz, inst.origin, inst.h)
+    A = p2p.Plan(xyz, ids, inst.k, dtype=dtype, layout=layout)
+    G = p2p.Plan.from_grid(xyz, inst.origin, inst.h, inst.k, dtype=dtype, layout=layout)
+    ta, tg = A.export(), G.export()
+    for key in ta:
+        assert np.array_equal(ta[key], tg[key]), key
+    assert A.info() == G.info()
+    q = dev(inst.q.astype(np.complex64 if dtype == torch.complex64 else np.complex128))
+    assert torch.equal(A.apply(q), G.apply(q))
+    # and the oracle's ids give the oracle's tables
+    ref = oracle.Plan(oracle.box_ids(inst.xyz, inst.origin, inst.h)).tables()
+    for key in ref:
+        assert np.array_equal(tg[key], ref[key]), key
+
+
+def test_plan_from_grid_errors():
+    xyz = np.random.default_rng(1).random((200, 3))
+    with pytest.raises(p2p.P2PError) as e:
+        p2p.Plan.from_grid(dev(xyz), (0.5, 0.0, 0.0), 0.25, 1.0)  # ids below 0
+    assert e.value.status == 2
+    nanx = xyz.copy()
+    nanx[7, 2] = np.inf
+    with pytest.raises(p2p.P2PError) as e:
+        p2p.Plan.from_grid(dev(nanx), (0.0, 0.0, 0.0), 0.25, 1.0)
+    assert e.value.status == 2
+    with pytest.raises(p2p.P2PError) as e:
+        p2p.Plan.from_grid(dev(xyz), (0.0, 0.0, 0.0), 1e-12, 1.0)  # ids past 2^21
+    assert e.value.status == 2
+    P = p2p.Plan.from_grid(dev(np.zeros((0, 3))), (0.0, 0.0, 0.0), 1.0, 1.0)
+    assert P.info()["n_boxes"] == 0
