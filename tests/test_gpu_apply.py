@@ -3,6 +3,7 @@
 Bars: relative L2 error <= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path
 (complex64 strengths promoted exactly to complex128 for the oracle).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -10,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+import paper_2403_01596_amd as p2p
 import workloads as W
 from cases import plan_cases
 from gpu_helpers import dev, gpu_apply, gpu_plan, rel_l2
@@ -103,3 +105,47 @@ def test_sphere_2m_sampled_rows():
         inf = P.info()
         assert inf["n_boxes"] > 50000 and inf["t_max"] > 64
         del P
+
+
+@pytest.mark.parametrize("layout", ["csr", "tiles"])
+def test_graph_capture_of_apply_and_backward(layout):
+    """p2p_apply and p2p_apply_backward allocate nothing and do not synchronise, so a
+    HIP graph can hold them: three replays, with eager work and new inputs between
+    them, each equal bitwise to an eager call on the same inputs."""
+    inst = W.sphere(40000, 32, 2 * math.pi * 10, seed=77)
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout)
+    q = dev(inst.q.astype(np.complex64))
+    g = dev(W.strengths(inst.n, 1, np.random.default_rng(3), np.complex64))
+    y = torch.empty_like(q)
+    dq = torch.empty_like(q)
+    dx = torch.empty((inst.n, 3), dtype=torch.float64, device="cuda")
+    lib = p2p.lib()
+
+    def calls():
+        s = torch.cuda.current_stream().cuda_stream
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        assert lib.p2p_apply(P.handle, p(q), p(y), 1, 1, ctypes.c_void_p(s)) == 0
+        assert lib.p2p_apply_backward(P.handle, p(q), p(g), p(dq), p(dx), 1, 1, ctypes.c_void_p(s)) == 0
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        calls()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls()
+    for rep in range(3):
+        q.mul_(1.5)
+        g.add_(0.25)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (y.clone(), dq.clone(), dx.clone())
+        ey = P.apply(q)
+        edq, edx = P.backward(q, g)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], ey), rep
+        assert torch.equal(got[1], edq), rep
+        assert torch.equal(got[2], edx), rep
