@@ -153,13 +153,16 @@ p2p_status p2p_plan_timing(p2p_plan plan, int enable);
 p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls);
 
 /* Batches: several complex64 plans (same layout, FP32) served together for nrhs
- * right-hand sides, with the near-field products on the matrix cores; every plan
- * must have been created with max_rhs >= nrhs, and count <= 32.  The plans stay
- * owned by the caller and must outlive the batch.  p2p_batch_apply(q, y): host
- * arrays of count device pointers, q[i] and y[i] are [n_i, nrhs] complex64 in
- * plan i's point order; one gather launch and one product launch, no
- * allocation and no synchronisation (capturable in a HIP graph).  Plans created
- * with max_rhs >= 16 use the same path from p2p_apply when nrhs >= 16. */
+ * right-hand sides: for every plan y = A_near q as in p2p_apply (paper sections
+ * 3.2-3.3, the same near pairs and kernel), each box's block of the product on the
+ * matrix cores.  Every plan must have been created with max_rhs >= nrhs, and
+ * count <= 32.  The plans stay owned by the caller and must outlive the batch.
+ * p2p_batch_apply(q, y): host arrays of count device pointers, q[i] and y[i] are
+ * [n_i, nrhs] complex64 in plan i's point order; one kernel launch that reads the
+ * strengths in that order, no allocation, no scratch memory and no
+ * synchronisation (capturable in a HIP graph, replayable with the same pointers).
+ * Plans created with max_rhs >= 16 use the same path from p2p_apply when
+ * nrhs >= 16. */
 typedef struct p2p_batch_s* p2p_batch;
 p2p_status p2p_batch_create(const p2p_plan* plans, int32_t count, int32_t nrhs, p2p_batch* out);
 p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y, void* stream);

@@ -30,15 +30,6 @@ p2p_status hip_fail(hipError_t e, const char* what);
     if (e_ != hipSuccess) return ::p2p::hip_fail(e_, #call);            \
   } while (0)
 
-// ---------------------------------------------------------------------------
-// plan
-// ---------------------------------------------------------------------------
-struct DeviceArena {
-  // Device memory from the stream-ordered pool; released in one go.
-  void* base = nullptr;
-  size_t bytes = 0;
-};
-
 }  // namespace p2p
 
 struct p2p_batch_s;
