@@ -718,27 +718,47 @@ __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict_
   key[T] = (uint64_t)(255 - b);
 }
 
-// Zero-distance pairs (self pairs included), FP64 coordinates.
+// Zero-distance pairs (self pairs included), FP64 coordinates, one wavefront per
+// box; one partial sum per workgroup.  self_only: points of distinct boxes cannot
+// coincide (their bounding boxes do not meet), so only the box's own points are
+// compared.
 __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict__ sx, int64_t n,
                                                     const int32_t* __restrict__ box_start,
                                                     const int32_t* __restrict__ nbr_start,
-                                                    const int32_t* __restrict__ nbr_idx, int32_t nb,
-                                                    uint64_t* __restrict__ zero) {
+                                                    const int32_t* __restrict__ nbr_idx, int32_t nb, bool self_only,
+                                                    uint64_t* __restrict__ part) {
+  __shared__ uint64_t lds[kWavesPerBlockPlan];
   const int64_t T = (int64_t)blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   uint32_t z = 0;
   if (T < nb) {
+    const int32_t e0 = self_only ? 0 : nbr_start[T], e1 = self_only ? 1 : nbr_start[T + 1];
     for (int32_t t = box_start[T]; t < box_start[T + 1]; ++t) {
       const double x = sx[t], y = sx[n + t], w = sx[2 * n + t];
-      for (int32_t e = nbr_start[T]; e < nbr_start[T + 1]; ++e) {
-        const int32_t S = nbr_idx[e];
+      for (int32_t e = e0; e < e1; ++e) {
+        const int32_t S = self_only ? (int32_t)T : nbr_idx[e];
         for (int32_t p = box_start[S] + lane; p < box_start[S + 1]; p += kWave)
           z += (sx[p] == x && sx[n + p] == y && sx[2 * n + p] == w) ? 1 : 0;
       }
     }
   }
-  z = wave_add63(z);
-  if (lane == kWave - 1 && z) atomicAdd((unsigned long long*)zero, (unsigned long long)z);
+  const uint64_t zb = block_combine63((uint64_t)wave_add63(z), lds, [](uint64_t a, uint64_t b) { return a + b; });
+  if (threadIdx.x == 0) part[blockIdx.x] = zb;
+}
+
+// out = sum of a[0..n), one workgroup: per-thread sums, then a tree in LDS.
+__global__ void __launch_bounds__(kBlock) k_sum_u64(const uint64_t* __restrict__ a, int64_t n,
+                                                 uint64_t* __restrict__ out) {
+  __shared__ uint64_t lds[kBlock];
+  uint64_t v = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) v += a[i];
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int half = kBlock / 2; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half) lds[threadIdx.x] += lds[threadIdx.x + half];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = lds[0];
 }
 
 __global__ void __launch_bounds__(kBlock) k_box_ids(const double* __restrict__ xyz, int64_t n3, double ox, double oy,
@@ -1065,14 +1085,18 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   if (P->n_pairs >= 0) return P2P_OK;
   ScopedBlock blk(s);
-  p2p_status rc = dev_alloc(&blk.p, sizeof(DevStatus));
+  const unsigned g = grid_for(std::max<int64_t>(P->B, 1), kWavesPerBlockPlan);
+  p2p_status rc = dev_alloc(&blk.p, sizeof(DevStatus) + sizeof(uint64_t) * g);
   if (rc != P2P_OK) return rc;
   DevStatus* status = (DevStatus*)blk.p;
+  uint64_t* part = (uint64_t*)((char*)blk.p + sizeof(DevStatus));
   hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, (uint32_t*)status,
                      (int64_t)(sizeof(DevStatus) / sizeof(uint32_t)), nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
-  if (P->B > 0)
-    hipLaunchKernelGGL(k_count_zero, dim3(grid_for(P->B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx64, P->n,
-                       P->box_start, P->nbr_start, P->nbr_idx, (int32_t)P->B, &status->zero);
+  if (P->B > 0) {
+    hipLaunchKernelGGL(k_count_zero, dim3(g), dim3(kBlock), 0, s, P->sx64, P->n, P->box_start, P->nbr_start,
+                       P->nbr_idx, (int32_t)P->B, !P->may_coincide, part);
+    hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->zero);
+  }
   P2P_HIP(hipGetLastError());
   DevStatus hs;
   rc = read_status(status, &hs, s);
