@@ -219,6 +219,22 @@ __device__ __forceinline__ float wave_sum63(float v) {
   v += dpp_f32<0x143>(v);  // row_bcast:31
   return v;
 }
+// Sums over the 64 lanes of two values at once: lane 31 receives the sum of a,
+// lane 63 the sum of b.  Exchanging lanes 32-63 of a with lanes 0-31 of b puts
+// the halves of a in lanes 0-31 and those of b in lanes 32-63, so one add and the
+// first five steps above (which leave each half's total in its last lane) serve
+// both values.
+__device__ __forceinline__ float wave_sum_pair(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  float v = __builtin_bit_cast(float, (unsigned)r[0]) + __builtin_bit_cast(float, (unsigned)r[1]);
+  v += dpp_f32<0xb1>(v);
+  v += dpp_f32<0x4e>(v);
+  v += dpp_f32<0x114>(v);
+  v += dpp_f32<0x118>(v);
+  v += dpp_f32<0x142>(v);
+  return v;
+}
 __device__ __forceinline__ double wave_sum63(double v) {
   v += dpp_f64<0xb1>(v);
   v += dpp_f64<0x4e>(v);
