@@ -53,14 +53,25 @@ __device__ __forceinline__ int64_t live(int64_t n, const int32_t* lim) {
   return lim ? min(n, (int64_t)*lim + 1) : n;
 }
 
+// One or two arrays of the same length scanned by the same launches; array y is
+// handled by the workgroups with blockIdx.y == y.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ part,
-                                                     const int32_t* __restrict__ lim) {
+struct ScanIO {
+  const T* in[2];
+  T* out[2];
+  T* part[2];   // workspace: one entry per tile
+  T* total[2];  // sum of the array (device), or null
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_scan_reduce(ScanIO<T> io, int64_t n, const int32_t* __restrict__ lim) {
   __shared__ T lds[kBlock / kWave];
+  const int y = blockIdx.y;
+  const T* __restrict__ in = io.in[y];
   int64_t base = (int64_t)blockIdx.x * kScanTile;
   n = live(n, lim);
   if (base >= n) {
-    if (threadIdx.x == 0) part[blockIdx.x] = T(0);
+    if (threadIdx.x == 0) io.part[y][blockIdx.x] = T(0);
     return;
   }
   T s = 0;
@@ -70,12 +81,14 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(const T* __restrict__ in
   }
   T tot;
   block_exclusive_scan<T>(s, lds, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (threadIdx.x == 0) io.part[y][blockIdx.x] = tot;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_partials(T* __restrict__ part, int64_t g, T* __restrict__ total_out) {
+__global__ void __launch_bounds__(kBlock) k_scan_partials(ScanIO<T> io, int64_t g) {
   __shared__ T lds[kBlock / kWave];
+  const int y = blockIdx.y;
+  T* __restrict__ part = io.part[y];
   T carry = 0;
   for (int64_t c = 0; c < g; c += kBlock) {
     int64_t e = c + threadIdx.x;
@@ -85,14 +98,16 @@ __global__ void __launch_bounds__(kBlock) k_scan_partials(T* __restrict__ part, 
     if (e < g) part[e] = ex + carry;
     carry += tot;
   }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
+  if (threadIdx.x == 0 && io.total[y]) *io.total[y] = carry;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_scan_apply(const T* __restrict__ in, int64_t n, const T* __restrict__ part,
-                                                    T* __restrict__ out, const int32_t* __restrict__ lim) {
+__global__ void __launch_bounds__(kBlock) k_scan_apply(ScanIO<T> io, int64_t n, const int32_t* __restrict__ lim) {
   // each thread owns kScanItems consecutive elements of the tile
   __shared__ T lds[kBlock / kWave];
+  const int y = blockIdx.y;
+  const T* in = io.in[y];
+  T* out = io.out[y];
   n = live(n, lim);
   if ((int64_t)blockIdx.x * kScanTile >= n) return;
   int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -104,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* __restrict__ in,
     s += v[r];
   }
   T tot;
-  T ex = block_exclusive_scan<T>(s, lds, &tot) + part[blockIdx.x];
+  T ex = block_exclusive_scan<T>(s, lds, &tot) + io.part[y][blockIdx.x];
   for (int r = 0; r < kScanItems; ++r) {
     int64_t e = base + r;
     if (e < n) out[e] = ex;
@@ -112,27 +127,37 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const T* __restrict__ in,
   }
 }
 
-// out[0..n) = exclusive prefix of in; *total = sum (device pointer, may be null).
-// part: workspace of at least grid_for(n, kScanTile) elements.  in == out allowed.
 template <typename T>
 __global__ void k_zero_one(T* p) {
   if (threadIdx.x == 0) *p = T(0);
 }
 
+// Exclusive prefix sums of io's first `arrays` arrays, each n long (in == out
+// allowed); totals where io.total is set.  lim: see live().
 template <typename T>
-static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s,
-                       const int32_t* lim = nullptr) {
+static p2p_status scan_arrays(const ScanIO<T>& io, int arrays, int64_t n, hipStream_t s,
+                              const int32_t* lim = nullptr) {
   if (n <= 0) {
-    if (total) hipLaunchKernelGGL(k_zero_one<T>, dim3(1), dim3(kWave), 0, s, total);
+    for (int y = 0; y < arrays; ++y)
+      if (io.total[y]) hipLaunchKernelGGL(k_zero_one<T>, dim3(1), dim3(kWave), 0, s, io.total[y]);
     P2P_HIP(hipGetLastError());
     return P2P_OK;
   }
-  unsigned g = grid_for(n, kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(g), dim3(kBlock), 0, s, in, n, part, lim);
-  hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, total);
-  hipLaunchKernelGGL(k_scan_apply<T>, dim3(g), dim3(kBlock), 0, s, in, n, part, out, lim);
+  const unsigned g = grid_for(n, kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(g, arrays), dim3(kBlock), 0, s, io, n, lim);
+  hipLaunchKernelGGL(k_scan_partials<T>, dim3(1, arrays), dim3(kBlock), 0, s, io, (int64_t)g);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3(g, arrays), dim3(kBlock), 0, s, io, n, lim);
   P2P_HIP(hipGetLastError());
   return P2P_OK;
+}
+
+// out[0..n) = exclusive prefix of in; *total = sum (device pointer, may be null).
+// part: workspace of at least grid_for(n, kScanTile) elements.  in == out allowed.
+template <typename T>
+static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s,
+                       const int32_t* lim = nullptr) {
+  const ScanIO<T> io{{in, nullptr}, {out, nullptr}, {part, nullptr}, {total, nullptr}};
+  return scan_arrays<T>(io, 1, n, s, lim);
 }
 
 // ---------------------------------------------------------------------------
@@ -585,13 +610,25 @@ __device__ __forceinline__ int32_t neighbour_lane(const uint64_t* __restrict__ b
 // slots and, from the bounding boxes, the largest per-axis coordinate difference
 // to any neighbour and whether two distinct boxes' bounding boxes intersect.
 // Filling pass: the neighbour indices in ascending order.
+// Fixed-point coordinate: X = rint(x * 2^-qexp), kept modulo 2^32.  Differences of
+// two such values taken modulo 2^32 are exact whenever the true difference is below
+// 2^31 in magnitude, which the choice of qexp guarantees for near pairs.
+__device__ __forceinline__ int32_t fixed_point(double x, int qexp) {
+  const double v = rint(ldexp(x, -qexp));
+  return (int32_t)(uint32_t)(uint64_t)(int64_t)v;
+}
+
+// FILL false: neighbour counts, neighbourhood sizes and the geometry bounds.  FILL
+// true: the lists themselves and, when sx32 is given, the fixed-point coordinates
+// of the box's own points.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box_key,
                                              const int32_t* __restrict__ box_start, const double* __restrict__ bb,
                                              const DevStatus* __restrict__ status, CellGrid grid,
                                              int32_t* __restrict__ cnt, int32_t* __restrict__ src,
                                              const int32_t* __restrict__ nbr_start, int32_t* __restrict__ nbr_idx,
-                                             Partial* __restrict__ part) {
+                                             Partial* __restrict__ part, const double* __restrict__ sx64,
+                                             int32_t* __restrict__ sx32, int64_t n, int qexp) {
   __shared__ uint64_t ldsl[kWavesPerBlockPlan];
   __shared__ double ldsd[kWavesPerBlockPlan];
   __shared__ uint32_t ldsu[kWavesPerBlockPlan];
@@ -613,6 +650,11 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
         rank += (Sj >= 0 && Sj < S) ? 1 : 0;
       }
       if (found) nbr_idx[ld_uniform(nbr_start + T) + rank] = S;
+      if (sx32) {
+        const int32_t p1 = ld_uniform(box_start + T + 1);
+        for (int32_t p = ld_uniform(box_start + T) + lane; p < p1; p += kWave)
+          for (int d = 0; d < 3; ++d) sx32[d * n + p] = fixed_point(sx64[d * n + p], qexp);
+      }
     } else {
       uint32_t ns = 0;
       double sep = 0.0;
@@ -657,17 +699,6 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
       p.overlap = overlap;
     }
   }
-}
-
-// Fixed-point coordinates: X = rint(x * 2^-qexp), kept modulo 2^32.  Differences of
-// two such values taken modulo 2^32 are exact whenever the true difference is
-// below 2^31 in magnitude, which the choice of qexp guarantees for near pairs.
-__global__ void __launch_bounds__(kBlock) k_fixed(const double* __restrict__ sx, int64_t n3, int qexp,
-                                               int32_t* __restrict__ fx) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n3) return;
-  const double v = rint(ldexp(sx[p], -qexp));
-  fx[p] = (int32_t)(uint32_t)(uint64_t)(int64_t)v;
 }
 
 // Replicated source lists: one wavefront per target box copies the points of its
@@ -1006,12 +1037,14 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   //         Entries past the last box stay zero, so scanning n entries gives the
   //         offsets of the B boxes and, at index B, the totals.
   hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
-                     nullptr, nullptr, part);
+                     nullptr, nullptr, part, nullptr, nullptr, n, 0);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
-  rc = scan<int32_t>(cnt, P->nbr_start, n + 1, part32, &status->nnz, s, &status->nbox);
-  if (rc != P2P_OK) return rc;
-  rc = scan<int32_t>(src, P->tile_start, n + 1, part32, nullptr, s, &status->nbox);
+  {  // both box-indexed arrays in one set of launches (partu is free once the sort is done)
+    const ScanIO<int32_t> io{{cnt, src}, {P->nbr_start, P->tile_start}, {part32, (int32_t*)partu},
+                             {&status->nnz, nullptr}};
+    rc = scan_arrays<int32_t>(io, 2, n + 1, s, &status->nbox);
+  }
   if (rc != P2P_OK) return rc;
 
   // second readback: sizes of the lists and the geometry bounds
@@ -1061,8 +1094,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   }
   hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
                      dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
-                     P->nbr_idx, part);
-  if (!f64) hipLaunchKernelGGL(k_fixed, dim3(grid_for(3 * n)), dim3(kBlock), 0, s, P->sx64, 3 * n, P->qexp, P->sx32);
+                     P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)
