@@ -490,13 +490,6 @@ __global__ void __launch_bounds__(kBlock) k_keys(const int32_t* __restrict__ ids
   }
 }
 
-template <typename K>
-__global__ void __launch_bounds__(kBlock) k_box_flags(const K* __restrict__ key, int64_t n,
-                                                   int32_t* __restrict__ flag) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p < n) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
-}
-
 // Dense cell table over the occupied id range plus a one-cell halo of empty
 // cells, so that the 27 lookups of a box need no range checks.
 struct CellGrid {
@@ -508,22 +501,67 @@ struct CellGrid {
   }
 };
 
-// excl holds the exclusive scan of the run-start flags: the box of a run start p is excl[p].
+// Box table from the sorted keys, over tiles of kScanTile keys (each thread owns
+// kScanItems consecutive ones): a run of equal keys is a box, and a key that
+// differs from the one before it starts a run.  First pass: run starts per tile;
+// after those counts are scanned, the second pass numbers each tile's run starts
+// in order and writes the box's key, its first point and its cell of the table.
 template <typename K>
-__global__ void __launch_bounds__(kBlock) k_box_write(const K* __restrict__ key, int64_t n,
-                                                   const int32_t* __restrict__ excl, uint64_t* __restrict__ box_key,
-                                                   int32_t* __restrict__ box_start,
-                                                   const DevStatus* __restrict__ status, CellGrid grid) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n) return;
-  const uint64_t k = key[p];
-  if (p == 0 || k != (uint64_t)key[p - 1]) {
-    const int32_t b = excl[p];
-    box_key[b] = k;
-    box_start[b] = (int32_t)p;
-    if (grid.table) grid.table[grid.cell(compact3(k), compact3(k >> 1), compact3(k >> 2))] = b;
+__device__ __forceinline__ int32_t run_starts(const K* __restrict__ key, int64_t n, int64_t base, uint32_t& mask) {
+  K prev = base > 0 && base - 1 < n ? key[base - 1] : K(0);
+  int32_t c = 0;
+  mask = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t e = base + r;
+    if (e < n) {
+      const K k = key[e];
+      if (e == 0 || k != prev) {
+        mask |= 1u << r;
+        ++c;
+      }
+      prev = k;
+    }
   }
-  if (p == n - 1) box_start[status->nbox] = (int32_t)n;
+  return c;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kBlock) k_runs_count(const K* __restrict__ key, int64_t n,
+                                                    int32_t* __restrict__ part) {
+  __shared__ int32_t lds[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t mask;
+  const int32_t c = run_starts(key, n, base, mask);
+  int32_t tot;
+  block_exclusive_scan<int32_t>(c, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// part: the tile counts, scanned; status->nbox: the number of boxes.
+template <typename K>
+__global__ void __launch_bounds__(kBlock) k_runs_write(const K* __restrict__ key, int64_t n,
+                                                    const int32_t* __restrict__ part, uint64_t* __restrict__ box_key,
+                                                    int32_t* __restrict__ box_start,
+                                                    const DevStatus* __restrict__ status, CellGrid grid) {
+  __shared__ int32_t lds[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t mask;
+  const int32_t c = run_starts(key, n, base, mask);
+  int32_t tot;
+  int32_t b = block_exclusive_scan<int32_t>(c, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    if (mask & (1u << r)) {
+      const int64_t e = base + r;
+      const uint64_t k = key[e];
+      box_key[b] = k;
+      box_start[b] = (int32_t)e;
+      if (grid.table) grid.table[grid.cell(compact3(k), compact3(k >> 1), compact3(k >> 2))] = b;
+      ++b;
+    }
+    if (base + r == n - 1) box_start[status->nbox] = (int32_t)n;
+  }
 }
 
 // One wavefront per box (grid-stride): sorted FP64 coordinates (SoA), the box's
@@ -933,7 +971,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   const int64_t g_rs = grid_for(n, kRsTile);
   const int64_t scan_parts = grid_for(std::max<int64_t>(256 * g_rs, n + 1), kScanTile);
   uint64_t *k0 = nullptr, *k1 = nullptr;
-  int32_t *v1 = nullptr, *flag = nullptr, *cnt = nullptr, *src = nullptr, *part32 = nullptr;
+  int32_t *v1 = nullptr, *cnt = nullptr, *src = nullptr, *part32 = nullptr;
   uint32_t *hist = nullptr, *partu = nullptr;
   double* bb = nullptr;
   DevStatus* status = nullptr;
@@ -944,7 +982,6 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     k0 = b.take<uint64_t>(n);
     k1 = b.take<uint64_t>(n);
     v1 = b.take<int32_t>(n);
-    flag = b.take<int32_t>(n + 1);
     cnt = b.take<int32_t>(n + 1);
     src = b.take<int32_t>(n + 1);
     hist = b.take<uint32_t>(256 * g_rs);
@@ -1017,18 +1054,22 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   if (rc != P2P_OK) return rc;
 
   // ---- 3. box table: runs of equal keys
-  if (sk.k32)
-    hipLaunchKernelGGL(k_box_flags<uint32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k32, n, flag);
-  else
-    hipLaunchKernelGGL(k_box_flags<uint64_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k64, n, flag);
-  rc = scan<int32_t>(flag, flag, n, part32, &status->nbox, s);
-  if (rc != P2P_OK) return rc;
-  if (sk.k32)
-    hipLaunchKernelGGL(k_box_write<uint32_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k32, n, flag, P->box_key,
-                       P->box_start, status, grid);
-  else
-    hipLaunchKernelGGL(k_box_write<uint64_t>, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k64, n, flag, P->box_key,
-                       P->box_start, status, grid);
+  {
+    const unsigned gt = grid_for(n, kScanTile);
+    if (sk.k32)
+      hipLaunchKernelGGL(k_runs_count<uint32_t>, dim3(gt), dim3(kBlock), 0, s, sk.k32, n, part32);
+    else
+      hipLaunchKernelGGL(k_runs_count<uint64_t>, dim3(gt), dim3(kBlock), 0, s, sk.k64, n, part32);
+    const ScanIO<int32_t> io{{nullptr, nullptr}, {nullptr, nullptr}, {part32, nullptr}, {&status->nbox, nullptr}};
+    hipLaunchKernelGGL(k_scan_partials<int32_t>, dim3(1, 1), dim3(kBlock), 0, s, io, (int64_t)gt);
+    if (sk.k32)
+      hipLaunchKernelGGL(k_runs_write<uint32_t>, dim3(gt), dim3(kBlock), 0, s, sk.k32, n, part32, P->box_key,
+                         P->box_start, status, grid);
+    else
+      hipLaunchKernelGGL(k_runs_write<uint64_t>, dim3(gt), dim3(kBlock), 0, s, sk.k64, n, part32, P->box_key,
+                         P->box_start, status, grid);
+    P2P_HIP(hipGetLastError());
+  }
   const unsigned gs = (unsigned)std::min<int64_t>(kGridStride, grid_for(n, kWavesPerBlockPlan));
   hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, status, P->sx64, bb,
                      part);
