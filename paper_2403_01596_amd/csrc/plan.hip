@@ -162,7 +162,9 @@ static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStr
 
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort of (key, i32 value), 8 bits per pass.  Per pass: digit
-// counts per tile, one scan over [digit][tile], then the scatter.  Keys are
+// counts per tile, a scan of each digit's row of tile counts (one workgroup per
+// digit, which also writes the digit's total), then the scatter, which turns
+// the 256 totals into the digits' start slots itself.  Keys are
 // narrowed to 32 bits by the first pass when the key bits in use allow it, and
 // the first pass makes the identity values itself.
 // ---------------------------------------------------------------------------
@@ -190,6 +192,32 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const KI* __restrict__ key, 
   hist[(int64_t)threadIdx.x * g + blockIdx.x] = h[threadIdx.x];
 }
 
+// hist is [digit][tile]; row d (workgroup d) becomes its exclusive prefix sums,
+// each thread scanning kScanItems consecutive tiles; total[d] gets the row's sum.
+__global__ void __launch_bounds__(kBlock) k_rs_rows(uint32_t* __restrict__ hist, int g, uint32_t* __restrict__ total) {
+  __shared__ uint32_t lds[kBlock / kWave];
+  uint32_t* __restrict__ row = hist + (int64_t)blockIdx.x * g;
+  uint32_t carry = 0;
+  for (int c = 0; c < g; c += kScanTile) {
+    const int base = c + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      v[r] = base + r < g ? row[base + r] : 0u;
+      sum += v[r];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<uint32_t>(sum, lds, &tot) + carry;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      if (base + r < g) row[base + r] = ex;
+      ex += v[r];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) total[blockIdx.x] = carry;
+}
+
 // Scatter one tile.  Wavefront w ranks the w-th quarter of the tile on its own, in
 // input order: the rank of a key among equal digits is the count of that digit in
 // the wavefront's earlier rounds (an LDS counter per digit) plus the lanes below
@@ -199,10 +227,15 @@ __global__ void __launch_bounds__(kBlock) k_rs_hist(const KI* __restrict__ key, 
 template <typename KI, typename KO>
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ kin, const int32_t* __restrict__ vin,
                                                     KO* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
-                                                    int shift, const uint32_t* __restrict__ offs, int g) {
+                                                    int shift, const uint32_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ dtotal, int g) {
   __shared__ uint32_t cnt[kBlock / kWave][256];
+  __shared__ uint32_t lds[kBlock / kWave];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
   for (int d = lane; d < 256; d += kWave) cnt[wave][d] = 0;
+  // thread tid: digit tid's count over all tiles, and this tile's start within it
+  const uint32_t dtot = dtotal[tid];
+  const uint32_t doff = offs[(int64_t)tid * g + blockIdx.x];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)wave * kRsWaveItems;
   // every load of the wavefront's quarter in flight before the ranking
@@ -233,9 +266,10 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ ki
     pos[r] = before + rank;
     if (valid && rank == 0) cnt[wave][d] = before + __popcll(peers);
   }
-  __syncthreads();
+  // the digits' start slots (the scan's barriers also order the counters above)
+  uint32_t all;
+  uint32_t run = block_exclusive_scan<uint32_t>(dtot, lds, &all) + doff;
   // thread tid: digit tid; the quarters' start slots, in order
-  uint32_t run = offs[(int64_t)tid * g + blockIdx.x];
   for (int w = 0; w < kBlock / kWave; ++w) {
     const uint32_t c = cnt[w][tid];
     cnt[w][tid] = run;
@@ -259,7 +293,8 @@ __global__ void __launch_bounds__(kBlock) k_iota(int32_t* __restrict__ v, int64_
 }
 
 // Sorts the keys k0[0..n) by their low `bits` bits; the stable order of the
-// positions lands in vals.  Workspace: kx (n u64), vx (n i32).  Returns in *sorted
+// positions lands in vals.  Workspace: kx (n u64), vx (n i32), hist (256 per tile
+// of kRsTile keys), part (256 digit totals).  Returns in *sorted
 // the sorted keys: 32-bit (in kx's storage) when bits <= 32, else 64-bit (k0 or kx).
 struct SortedKeys {
   const uint32_t* k32;
@@ -292,21 +327,20 @@ static p2p_status radix_sort(uint64_t* k0, int32_t* vals, uint64_t* kx, int32_t*
       hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(g), dim3(kBlock), 0, s, cur32, n, shift, hist, g);
     else
       hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(g), dim3(kBlock), 0, s, cur64, n, shift, hist, g);
-    p2p_status st = scan<uint32_t>(hist, hist, (int64_t)256 * g, part, nullptr, s);
-    if (st != P2P_OK) return st;
+    hipLaunchKernelGGL(k_rs_rows, dim3(256), dim3(kBlock), 0, s, hist, g, part);
     if (narrow) {
       uint32_t* kout = (p % 2 == 0) ? a32 : b32;
       if (cur32)
         hipLaunchKernelGGL((k_rs_scatter<uint32_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur32, vcur, kout, vout, n,
-                           shift, hist, g);
+                           shift, hist, part, g);
       else
         hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
-                           shift, hist, g);
+                           shift, hist, part, g);
       cur32 = kout;
     } else {
       uint64_t* kout = (p % 2 == 0) ? kx : k0;
       hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint64_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
-                         shift, hist, g);
+                         shift, hist, part, g);
       cur64 = kout;
     }
     P2P_HIP(hipGetLastError());
@@ -985,7 +1019,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     cnt = b.take<int32_t>(n + 1);
     src = b.take<int32_t>(n + 1);
     hist = b.take<uint32_t>(256 * g_rs);
-    partu = b.take<uint32_t>(scan_parts);
+    partu = b.take<uint32_t>(std::max<int64_t>(scan_parts, 256));
     part32 = b.take<int32_t>(scan_parts);
     bb = b.take<double>(6 * std::max<int64_t>(n, 1));
   };
