@@ -221,23 +221,29 @@ __global__ void __launch_bounds__(kBlock) k_rs_rows(uint32_t* __restrict__ hist,
 // Scatter one tile.  Wavefront w ranks the w-th quarter of the tile on its own, in
 // input order: the rank of a key among equal digits is the count of that digit in
 // the wavefront's earlier rounds (an LDS counter per digit) plus the lanes below
-// it with the same digit (wave ballots).  Then the quarters are stacked in order
-// under the tile's offset for each digit, so equal digits keep their input order
-// (stability).  vin null: the values are the input positions.
+// it with the same digit (wave ballots).  The quarters are stacked in order under
+// each digit's start, so equal digits keep their input order (stability).  The
+// tile is first laid out sorted in LDS and then written with consecutive threads
+// on consecutive slots, so each digit's run goes out as whole lines rather than
+// one scattered element per lane.  vin null: the values are the input positions.
 template <typename KI, typename KO>
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ kin, const int32_t* __restrict__ vin,
                                                     KO* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
                                                     int shift, const uint32_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ dtotal, int g) {
   __shared__ uint32_t cnt[kBlock / kWave][256];
-  __shared__ uint32_t lds[kBlock / kWave];
+  __shared__ uint64_t lds[kBlock / kWave];
+  __shared__ uint32_t delta[256];
+  __shared__ KO sk[kRsTile];
+  __shared__ int32_t sv[kRsTile];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
   for (int d = lane; d < 256; d += kWave) cnt[wave][d] = 0;
   // thread tid: digit tid's count over all tiles, and this tile's start within it
   const uint32_t dtot = dtotal[tid];
   const uint32_t doff = offs[(int64_t)tid * g + blockIdx.x];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)wave * kRsWaveItems;
+  const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+  const int64_t base = tile0 + (int64_t)wave * kRsWaveItems;
   // every load of the wavefront's quarter in flight before the ranking
   KI k[kRsItems];
   int32_t v[kRsItems];
@@ -266,23 +272,44 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ ki
     pos[r] = before + rank;
     if (valid && rank == 0) cnt[wave][d] = before + __popcll(peers);
   }
-  // the digits' start slots (the scan's barriers also order the counters above)
-  uint32_t all;
-  uint32_t run = block_exclusive_scan<uint32_t>(dtot, lds, &all) + doff;
-  // thread tid: digit tid; the quarters' start slots, in order
+  __syncthreads();
+  // thread tid, digit tid: its count in each quarter; one scan gives both the
+  // digit's start among all keys (high half) and within the tile (low half)
+  uint32_t c[kBlock / kWave], tcount = 0;
+#pragma unroll
   for (int w = 0; w < kBlock / kWave; ++w) {
-    const uint32_t c = cnt[w][tid];
-    cnt[w][tid] = run;
-    run += c;
+    c[w] = cnt[w][tid];
+    tcount += c[w];
+  }
+  uint64_t all;
+  const uint64_t both = block_exclusive_scan<uint64_t>(((uint64_t)dtot << 32) | tcount, lds, &all);
+  const uint32_t lstart = (uint32_t)both;
+  delta[tid] = (uint32_t)(both >> 32) + doff - lstart;
+  uint32_t run = lstart;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    cnt[w][tid] = run;  // the quarter's first slot of this digit within the tile
+    run += c[w];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRsItems; ++r) {
-    const int64_t e = base + (int64_t)r * kWave + lane;
-    if (e < n) {
+    if (base + (int64_t)r * kWave + lane < n) {
       const uint32_t at = cnt[wave][(uint32_t)(k[r] >> shift) & 255u] + pos[r];
-      kout[at] = (KO)k[r];
-      vout[at] = v[r];
+      sk[at] = (KO)k[r];
+      sv[at] = v[r];
+    }
+  }
+  __syncthreads();
+  const int live = (int)min<int64_t>(kRsTile, n - tile0);
+#pragma unroll
+  for (int r = 0; r < kRsItems; ++r) {
+    const int i = r * kBlock + tid;
+    if (i < live) {
+      const KO kk = sk[i];
+      const uint32_t at = delta[(uint32_t)(kk >> shift) & 255u] + (uint32_t)i;
+      kout[at] = kk;
+      vout[at] = sv[i];
     }
   }
 }
