@@ -641,11 +641,10 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
   for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
        T += gridDim.x * kWavesPerBlockPlan) {
     const int32_t p0 = box_start[T], p1 = box_start[T + 1];
-    // lanes past the box's last point repeat its first point
     double lo[3], hi[3];
-    {
-      const int64_t i0 = perm[p0];
-      for (int d = 0; d < 3; ++d) lo[d] = hi[d] = xyz[3 * i0 + d];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = INFINITY;
+      hi[d] = -INFINITY;
     }
     for (int32_t p = p0 + lane; p < p1; p += kWave) {
       const int64_t i = perm[p];
