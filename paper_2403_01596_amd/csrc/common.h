@@ -210,6 +210,46 @@ __device__ __forceinline__ uint32_t wave_add63(uint32_t v) {
   return v;
 }
 
+// The same reductions over each half of the wavefront separately (lanes 0-31 and
+// 32-63), for code that works on two items per wavefront: the first five steps
+// only.  Lane 31 then holds the lower half's result and lane 63 the upper half's:
+// row broadcast 15 combines row 0 into row 1 and row 2 into row 3, and what it
+// carries from row 1 into row 2 reaches neither lane.
+__device__ __forceinline__ uint32_t half_add(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xf, 0xf, true);
+  return v;
+}
+__device__ __forceinline__ uint32_t half_or(uint32_t v) {
+  v |= dpp_keep_u32<0xb1>(v);
+  v |= dpp_keep_u32<0x4e>(v);
+  v |= dpp_keep_u32<0x114>(v);
+  v |= dpp_keep_u32<0x118>(v);
+  v |= dpp_keep_u32<0x142>(v);
+  return v;
+}
+__device__ __forceinline__ double half_max(double v) {
+  v = fmax(v, dpp_keep_f64<0xb1>(v));
+  v = fmax(v, dpp_keep_f64<0x4e>(v));
+  v = fmax(v, dpp_keep_f64<0x114>(v));
+  v = fmax(v, dpp_keep_f64<0x118>(v));
+  v = fmax(v, dpp_keep_f64<0x142>(v));
+  return v;
+}
+// Lane 31's value (wave-uniform).
+__device__ __forceinline__ uint32_t lane31(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 31); }
+__device__ __forceinline__ uint64_t lane31(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 31);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 31);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double lane31(double v) {
+  return __builtin_bit_cast(double, lane31(__builtin_bit_cast(uint64_t, v)));
+}
+
 __device__ __forceinline__ float wave_sum63(float v) {
   v += dpp_f32<0xb1>(v);   // quad_perm [1,0,3,2]
   v += dpp_f32<0x4e>(v);   // quad_perm [2,3,0,1]

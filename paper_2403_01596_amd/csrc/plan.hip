@@ -625,28 +625,30 @@ __global__ void __launch_bounds__(kBlock) k_runs_write(const K* __restrict__ key
   }
 }
 
-// One wavefront per box (grid-stride): sorted FP64 coordinates (SoA), the box's
-// bounding box, the largest occupancy and the largest |coordinate|.
+// One box per half wavefront (grid-stride): sorted FP64 coordinates (SoA), the
+// box's bounding box, the largest occupancy and the largest |coordinate|.
 __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ xyz, const int32_t* __restrict__ perm,
                                                   int64_t n, const int32_t* __restrict__ box_start,
                                                   const DevStatus* __restrict__ status, double* __restrict__ sx,
                                                   double* __restrict__ bb, Partial* __restrict__ part) {
   __shared__ double ldsd[kWavesPerBlockPlan];
   __shared__ uint32_t ldsu[kWavesPerBlockPlan];
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = threadIdx.x & (kWave - 1), half = lane >> 5, h = lane & 31;
   const int32_t nb = status->nbox;
   uint32_t tmax = 0;
   bool bad_x = false;
   double amax = 0.0;
-  for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
-       T += gridDim.x * kWavesPerBlockPlan) {
-    const int32_t p0 = box_start[T], p1 = box_start[T + 1];
+  for (int32_t T0 = 2 * (blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave); T0 < nb;
+       T0 += 2 * gridDim.x * kWavesPerBlockPlan) {
+    const int32_t T = T0 + half;
+    const bool live = T < nb;
+    const int32_t p0 = live ? box_start[T] : 0, p1 = live ? box_start[T + 1] : 0;
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
       lo[d] = INFINITY;
       hi[d] = -INFINITY;
     }
-    for (int32_t p = p0 + lane; p < p1; p += kWave) {
+    for (int32_t p = p0 + h; p < p1; p += 32) {
       const int64_t i = perm[p];
       for (int d = 0; d < 3; ++d) {
         const double v = xyz[3 * i + d];
@@ -657,10 +659,10 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
       }
     }
     for (int d = 0; d < 3; ++d) {
-      lo[d] = -wave_max63(-lo[d]);
-      hi[d] = wave_max63(hi[d]);
+      lo[d] = -half_max(-lo[d]);
+      hi[d] = half_max(hi[d]);
     }
-    if (lane == kWave - 1) {
+    if (h == 31 && live) {
       for (int d = 0; d < 3; ++d) {
         bb[6 * (int64_t)T + d] = lo[d];
         bb[6 * (int64_t)T + 3 + d] = hi[d];
@@ -669,6 +671,9 @@ __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ 
       tmax = max(tmax, (uint32_t)(p1 - p0));
     }
   }
+  // lanes 31 and 63 hold the two halves' results; lane 63 takes both
+  tmax = max(tmax, lane31(tmax));
+  amax = fmax(amax, lane31(amax));
   tmax = block_combine63(tmax, ldsu, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
   amax = block_combine63(amax, ldsd, [](double x, double y) { return fmax(x, y); });
   const uint32_t bx = block_combine63(wave_or63(bad_x ? 2u : 0u), ldsu, [](uint32_t x, uint32_t y) { return x | y; });
@@ -718,7 +723,8 @@ __device__ __forceinline__ int32_t fixed_point(double x, int qexp) {
 
 // FILL false: neighbour counts, neighbourhood sizes and the geometry bounds.  FILL
 // true: the lists themselves and, when sx32 is given, the fixed-point coordinates
-// of the box's own points.
+// of the box's own points.  Each half of a wavefront takes one box (27 of its 32
+// lanes look up the neighbours), so a wavefront has two boxes' lookups in flight.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box_key,
                                              const int32_t* __restrict__ box_start, const double* __restrict__ bb,
@@ -730,27 +736,31 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
   __shared__ uint64_t ldsl[kWavesPerBlockPlan];
   __shared__ double ldsd[kWavesPerBlockPlan];
   __shared__ uint32_t ldsu[kWavesPerBlockPlan];
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = threadIdx.x & (kWave - 1), half = lane >> 5, h = lane & 31;
+  const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
   const int32_t nb = status->nbox;
   uint64_t slots = 0, srcsum = 0;
   double msep = 0.0;
   uint32_t overlap = 0;
-  for (int32_t T = blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave; T < nb;
-       T += gridDim.x * kWavesPerBlockPlan) {
-    const uint64_t kT = ld_uniform(box_key + T);
-    const int32_t S = neighbour_lane(box_key, nb, grid, kT, lane);
+  for (int32_t T0 = 2 * (blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave); T0 < nb;
+       T0 += 2 * gridDim.x * kWavesPerBlockPlan) {
+    const int32_t T = T0 + half;
+    const bool live = T < nb;
+    const uint64_t kT = live ? box_key[T] : 0;
+    const int32_t S = live ? neighbour_lane(box_key, nb, grid, kT, h) : -1;
     const bool found = S >= 0;
     if (FILL) {
-      // rank among the found neighbours by box index (= by key)
+      // rank among the found neighbours of the same box by box index (= by key)
       int32_t rank = 0;
       for (int j = 0; j < 27; ++j) {
-        const int32_t Sj = __builtin_amdgcn_readlane(S, j);
+        const int32_t a = __builtin_amdgcn_readlane(S, j), b = __builtin_amdgcn_readlane(S, 32 + j);
+        const int32_t Sj = half ? b : a;
         rank += (Sj >= 0 && Sj < S) ? 1 : 0;
       }
-      if (found) nbr_idx[ld_uniform(nbr_start + T) + rank] = S;
-      if (sx32) {
-        const int32_t p1 = ld_uniform(box_start + T + 1);
-        for (int32_t p = ld_uniform(box_start + T) + lane; p < p1; p += kWave)
+      if (found) nbr_idx[nbr_start[T] + rank] = S;
+      if (sx32 && live) {
+        const int32_t p1 = box_start[T + 1];
+        for (int32_t p = box_start[T] + h; p < p1; p += 32)
           for (int d = 0; d < 3; ++d) sx32[d * n + p] = fixed_point(sx64[d * n + p], qexp);
       }
     } else {
@@ -768,11 +778,11 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
         }
         meet = inter ? 1u : 0u;
       }
-      const uint32_t c = (uint32_t)__popcll(__ballot(found));
-      ns = wave_add63(ns);
-      sep = wave_max63(sep);
-      meet = wave_or63(meet);
-      if (lane == kWave - 1) {
+      const uint32_t c = (uint32_t)__popcll(__ballot(found) & hmask);
+      ns = half_add(ns);
+      sep = half_max(sep);
+      meet = half_or(meet);
+      if (h == 31 && live) {
         const int32_t nT = box_start[T + 1] - box_start[T];
         cnt[T] = (int32_t)c;
         src[T] = (int32_t)ns;
@@ -784,6 +794,11 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
     }
   }
   if (!FILL) {
+    // lanes 31 and 63 hold the two halves' sums; lane 63 takes both
+    slots += lane31(slots);
+    srcsum += lane31(srcsum);
+    msep = fmax(msep, lane31(msep));
+    overlap |= lane31(overlap);
     auto add = [](uint64_t x, uint64_t y) { return x + y; };
     slots = block_combine63(slots, ldsl, add);
     srcsum = block_combine63(srcsum, ldsl, add);
