@@ -59,6 +59,10 @@ PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 982 Gpair/s
 FLOPS_PER_PAIR_RHS = 8
 PEAK_MFMA_F32 = 157.3e12
 
+# Untimed steps run for this long before the warm-up steps: the GPU leaves idle on
+# a lower clock and takes tens of milliseconds to reach its steady one.
+SPIN_UP_S = 0.25
+
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_counters.md")
 KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
                   "paper_2403_01596_amd/csrc/common.h"]
@@ -245,8 +249,8 @@ def measure_layouts(p2p, W, torch, reps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-mrhs", action="store_true", help="skip the multi-right-hand-side batch")
@@ -309,7 +313,13 @@ def main():
         plan.close()
         return y
 
-    # ---- the step: box ids + plan + FP32 apply + release
+    # ---- the step: box ids + plan + FP32 apply + release.  Untimed steps for a
+    # fixed spell first, so that the timed ones run at the steady clock rather than
+    # on the ramp out of idle, then the W warm-up steps.
+    spin_end = time.perf_counter() + SPIN_UP_S
+    while time.perf_counter() < spin_end:
+        step()
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -173,9 +173,11 @@ constexpr int kRsTile = kBlock * kRsItems;
 constexpr int kRsWaveItems = kRsItems * kWave;  // keys of one wavefront's part of a tile
 
 template <typename KI>
-__global__ void __launch_bounds__(kBlock) k_rs_hist(const KI* __restrict__ key, int64_t n, int shift,
+__global__ void __launch_bounds__(kBlock) k_rs_hist(const KI* __restrict__ key, int64_t n,
+                                                 const int32_t* __restrict__ lim, int shift,
                                                  uint32_t* __restrict__ hist, int g) {
   __shared__ uint32_t h[256];
+  if (lim) n = min(n, (int64_t)*lim);
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRsTile;
@@ -229,7 +231,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_rows(uint32_t* __restrict__ hist,
 template <typename KI, typename KO>
 __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ kin, const int32_t* __restrict__ vin,
                                                     KO* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
-                                                    int shift, const uint32_t* __restrict__ offs,
+                                                    const int32_t* __restrict__ lim, int shift,
+                                                    const uint32_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ dtotal, int g) {
   __shared__ uint32_t cnt[kBlock / kWave][256];
   __shared__ uint64_t lds[kBlock / kWave];
@@ -237,6 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const KI* __restrict__ ki
   __shared__ KO sk[kRsTile];
   __shared__ int32_t sv[kRsTile];
   const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  if (lim) n = min(n, (int64_t)*lim);
   for (int d = lane; d < 256; d += kWave) cnt[wave][d] = 0;
   // thread tid: digit tid's count over all tiles, and this tile's start within it
   const uint32_t dtot = dtotal[tid];
@@ -321,7 +325,8 @@ __global__ void __launch_bounds__(kBlock) k_iota(int32_t* __restrict__ v, int64_
 
 // Sorts the keys k0[0..n) by their low `bits` bits; the stable order of the
 // positions lands in vals.  Workspace: kx (n u64), vx (n i32), hist (256 per tile
-// of kRsTile keys), part (256 digit totals).  Returns in *sorted
+// of kRsTile keys), part (256 digit totals).  lim (optional, device): the count of
+// keys actually sorted is min(n, *lim); n sizes the launches.  Returns in *sorted
 // the sorted keys: 32-bit (in kx's storage) when bits <= 32, else 64-bit (k0 or kx).
 struct SortedKeys {
   const uint32_t* k32;
@@ -329,7 +334,8 @@ struct SortedKeys {
 };
 
 static p2p_status radix_sort(uint64_t* k0, int32_t* vals, uint64_t* kx, int32_t* vx, int64_t n, int bits,
-                             uint32_t* hist, uint32_t* part, SortedKeys* sorted, hipStream_t s) {
+                             uint32_t* hist, uint32_t* part, SortedKeys* sorted, hipStream_t s,
+                             const int32_t* lim = nullptr) {
   const int passes = bits <= 0 ? 0 : (bits + 7) / 8;
   const bool narrow = bits <= 32;
   sorted->k32 = nullptr;
@@ -351,23 +357,23 @@ static p2p_status radix_sort(uint64_t* k0, int32_t* vals, uint64_t* kx, int32_t*
     // the last pass writes vals, the ones before alternate backwards from it
     int32_t* vout = ((passes - 1 - p) % 2 == 0) ? vals : vx;
     if (cur32)
-      hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(g), dim3(kBlock), 0, s, cur32, n, shift, hist, g);
+      hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(g), dim3(kBlock), 0, s, cur32, n, lim, shift, hist, g);
     else
-      hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(g), dim3(kBlock), 0, s, cur64, n, shift, hist, g);
+      hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(g), dim3(kBlock), 0, s, cur64, n, lim, shift, hist, g);
     hipLaunchKernelGGL(k_rs_rows, dim3(256), dim3(kBlock), 0, s, hist, g, part);
     if (narrow) {
       uint32_t* kout = (p % 2 == 0) ? a32 : b32;
       if (cur32)
         hipLaunchKernelGGL((k_rs_scatter<uint32_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur32, vcur, kout, vout, n,
-                           shift, hist, part, g);
+                           lim, shift, hist, part, g);
       else
         hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint32_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
-                           shift, hist, part, g);
+                           lim, shift, hist, part, g);
       cur32 = kout;
     } else {
       uint64_t* kout = (p % 2 == 0) ? kx : k0;
       hipLaunchKernelGGL((k_rs_scatter<uint64_t, uint64_t>), dim3(g), dim3(kBlock), 0, s, cur64, vcur, kout, vout, n,
-                         shift, hist, part, g);
+                         lim, shift, hist, part, g);
       cur64 = kout;
     }
     P2P_HIP(hipGetLastError());
@@ -742,6 +748,10 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
   uint64_t slots = 0, srcsum = 0;
   double msep = 0.0;
   uint32_t overlap = 0;
+  if (!FILL && blockIdx.x == 0 && threadIdx.x == 0) {  // the scans' last entry
+    cnt[nb] = 0;
+    src[nb] = 0;
+  }
   for (int32_t T0 = 2 * (blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave); T0 < nb;
        T0 += 2 * gridDim.x * kWavesPerBlockPlan) {
     const int32_t T = T0 + half;
@@ -853,10 +863,11 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
 // Processing order of the sweep: boxes in decreasing order of their pair slots,
 // bucketed on a log scale (8 buckets per octave), Morton order inside a bucket.
 __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict__ box_start,
-                                                   const int32_t* __restrict__ src, int32_t nb,
+                                                   const int32_t* __restrict__ src,
+                                                   const DevStatus* __restrict__ status,
                                                    uint64_t* __restrict__ key) {
   const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (T >= nb) return;
+  if (T >= status->nbox) return;
   const double c = (double)(box_start[T + 1] - box_start[T]) * (double)src[T];
   const int b = (int)fmin(255.0, floor(log2(c + 1.0) * 8.0));
   key[T] = (uint64_t)(255 - b);
@@ -980,6 +991,29 @@ p2p_status read_status(const DevStatus* dev, DevStatus* host, hipStream_t s) {
   return P2P_OK;
 }
 
+// A status copy to the host that the host waits for through an event, so that
+// work enqueued after the copy overlaps the wait.
+struct StatusCopy {
+  StagingLock st;
+  hipEvent_t ev = nullptr;
+  DevStatus pageable;  // target when no pinned staging buffer could be had
+  ~StatusCopy() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  p2p_status start(const DevStatus* dev, hipStream_t s) {
+    st = staging(sizeof(DevStatus));
+    P2P_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    P2P_HIP(hipMemcpyAsync(st.host ? st.host : (void*)&pageable, dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipEventRecord(ev, s));
+    return P2P_OK;
+  }
+  p2p_status finish(DevStatus* host) {
+    P2P_HIP(hipEventSynchronize(ev));
+    std::memcpy(host, st.host ? st.host : (void*)&pageable, sizeof(DevStatus));
+    return P2P_OK;
+  }
+};
+
 int bit_length(uint32_t v) {
   int b = 0;
   while (v) {
@@ -1074,7 +1108,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   // status block and partial rows are contiguous in the scratch block
   const int64_t zero_words = (int64_t)(((char*)(part + kGridStride) - (char*)status) / sizeof(uint32_t));
   hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(n + 1))), dim3(kBlock), 0, s,
-                     (uint32_t*)status, zero_words, cnt, src, n + 1, nullptr, (int64_t)0);
+                     (uint32_t*)status, zero_words, nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
   if (n == 0) {  // offsets of an empty plan: box_start = nbr_start = tile_start = {0}
     hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, nullptr, (int64_t)0, P->box_start, P->nbr_start,
                        (int64_t)1, nullptr, (int64_t)0);
@@ -1150,8 +1184,8 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
                      part);
 
   // ---- 4. neighbour counts, neighbourhood source counts, separation bound.
-  //         Entries past the last box stay zero, so scanning n entries gives the
-  //         offsets of the B boxes and, at index B, the totals.
+  //         The counting pass also zeroes entry B, so scanning B + 1 entries gives
+  //         the offsets of the B boxes and, at index B, the totals.
   hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
                      nullptr, nullptr, part, nullptr, nullptr, n, 0);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
@@ -1163,9 +1197,21 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   }
   if (rc != P2P_OK) return rc;
 
-  // second readback: sizes of the lists and the geometry bounds
-  rc = read_status(status, &hs, s);
-  if (rc != P2P_OK) return rc;
+  // second readback: sizes of the lists and the geometry bounds.  The processing
+  // order of the sweep (boxes with the most pair slots first: one stable 8-bit
+  // radix pass over cost keys, with the box count read on the device) is enqueued
+  // behind the copy and runs while the host waits for it.
+  {
+    StatusCopy copy;
+    rc = copy.start(status, s);
+    if (rc != P2P_OK) return rc;
+    hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, P->box_start, src, status, k0);
+    P2P_HIP(hipGetLastError());
+    rc = radix_sort(k0, P->work, k1, v1, n, 8, hist, partu, &sk, s, &status->nbox);
+    if (rc != P2P_OK) return rc;
+    rc = copy.finish(&hs);
+    if (rc != P2P_OK) return rc;
+  }
   if (hs.st[ST_BAD_X]) return fail(P2P_ERR_RANGE, "a coordinate is not finite");
   const int32_t B = hs.nbox;
   P->B = B;
@@ -1220,11 +1266,6 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
       hipLaunchKernelGGL(k_tile_fill<false>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
   }
-  // processing order: most pair slots first (one 8-bit radix pass, stable)
-  hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(B)), dim3(kBlock), 0, s, P->box_start, src, B, k0);
-  P2P_HIP(hipGetLastError());
-  rc = radix_sort(k0, P->work, k1, v1, B, 8, hist, partu, &sk, s);
-  if (rc != P2P_OK) return rc;
   P2P_HIP(hipGetLastError());
   P2P_HIP(hipStreamSynchronize(s));
   return P2P_OK;
