@@ -69,6 +69,19 @@ struct F32 {
   }
 };
 
+// sin(2 pi x) and cos(2 pi x) for |x| <= 1/4 from their Taylor series in x:
+// coefficients (2 pi)^n / n! with alternating signs, each correctly rounded to
+// double.  The first omitted terms are below 1.3e-18 (sin, x^23) and 1.9e-17 (cos,
+// x^22) in magnitude on that interval.
+constexpr double kSinTurn[11] = {0x1.921fb54442d18p+2,  -0x1.4abbce625be53p+5, 0x1.466bc6775aae2p+6,
+                                 -0x1.32d2cce62bd86p+6, 0x1.50783487ee782p+5,  -0x1.e3074fde8871fp+3,
+                                 0x1.e8f434d018d63p+1,  -0x1.6fadb9f155744p-1, 0x1.aaec32af93359p-4,
+                                 -0x1.8a404211f9547p-7, 0x1.2877020d52cf0p-10};
+constexpr double kCosTurn[11] = {0x1.0000000000000p+0,  -0x1.3bd3cc9be45dep+4, 0x1.03c1f081b5ac4p+6,
+                                 -0x1.55d3c7e3cbffap+6, 0x1.e1f506891babbp+5,  -0x1.a6d1f2a204a8cp+4,
+                                 0x1.f9d38a3763cc3p+2,  -0x1.b6e24f44b128fp+0, 0x1.20c62c2f2d7f5p-2,
+                                 -0x1.2a0c591af8314p-5, 0x1.ef6e308d6d1c4p-9};
+
 struct F64 {
   using coord = double;
   using real = double;
@@ -77,20 +90,57 @@ struct F64 {
   struct Geo {
     double dx, dy, dz, rinv, c, s, kr;
   };
-  // k: the wavenumber itself; coordinates are the caller's FP64 values, and the
-  // difference is formed exactly as in the definition, x_target - x_source.
+  // kt: k / (2 pi), the phase in turns per unit of distance.  Coordinates are the
+  // caller's FP64 values, and the difference is formed exactly as in the
+  // definition, x_target - x_source.
   template <bool HELM, bool MASK>
   __device__ static __forceinline__ Geo geo(double tx, double ty, double tz, double sx, double sy, double sz,
-                                            double k) {
+                                            double kt) {
     Geo g;
     g.dx = tx - sx;
     g.dy = ty - sy;
     g.dz = tz - sz;
-    const double r2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
-    g.rinv = (!MASK || r2 > 0.0) ? rsqrt(r2) : 0.0;
+    const double r2 = __builtin_fma(g.dz, g.dz, __builtin_fma(g.dy, g.dy, g.dx * g.dx));
+    // 1/r: the hardware estimate y refined by one third-order step,
+    // y (1 + e/2 + 3e^2/8) with e = 1 - r2 y^2 (the series of (1 - e)^(-1/2)).
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2 * y, y, 1.0);
+    const double ri = __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+    g.rinv = MASK ? ((r2 > 0.0) ? ri : 0.0) : ri;
     if (HELM) {
-      g.kr = k * (r2 * g.rinv);
-      sincos(g.kr, &g.s, &g.c);
+      // phase t in turns; t = h/2 + x with h the nearest whole number of half
+      // turns (so x = t - h/2 is exact and |x| <= 1/4), and an odd h flips the
+      // signs of both sin and cos
+      const double t = kt * (r2 * g.rinv);
+      const double h = __builtin_rint(t + t);
+      const double x = __builtin_fma(-0.5, h, t);
+      const double x2 = x * x;
+      // Estrin's scheme (pairs of terms in x2, then x4 and x8): two multiplications
+      // more than Horner's rule, and much shorter dependency chains
+      const double x4 = x2 * x2, x8 = x4 * x4;
+      const double s01 = __builtin_fma(kSinTurn[1], x2, kSinTurn[0]);
+      const double s23 = __builtin_fma(kSinTurn[3], x2, kSinTurn[2]);
+      const double s45 = __builtin_fma(kSinTurn[5], x2, kSinTurn[4]);
+      const double s67 = __builtin_fma(kSinTurn[7], x2, kSinTurn[6]);
+      const double s89 = __builtin_fma(kSinTurn[9], x2, kSinTurn[8]);
+      const double s0_3 = __builtin_fma(s23, x4, s01);
+      const double s4_7 = __builtin_fma(s67, x4, s45);
+      const double s8_10 = __builtin_fma(kSinTurn[10], x4, s89);
+      const double ps = __builtin_fma(__builtin_fma(s8_10, x8, s4_7), x8, s0_3);
+      const double c01 = __builtin_fma(kCosTurn[1], x2, kCosTurn[0]);
+      const double c23 = __builtin_fma(kCosTurn[3], x2, kCosTurn[2]);
+      const double c45 = __builtin_fma(kCosTurn[5], x2, kCosTurn[4]);
+      const double c67 = __builtin_fma(kCosTurn[7], x2, kCosTurn[6]);
+      const double c89 = __builtin_fma(kCosTurn[9], x2, kCosTurn[8]);
+      const double c0_3 = __builtin_fma(c23, x4, c01);
+      const double c4_7 = __builtin_fma(c67, x4, c45);
+      const double c8_10 = __builtin_fma(kCosTurn[10], x4, c89);
+      const double pc = __builtin_fma(__builtin_fma(c8_10, x8, c4_7), x8, c0_3);
+      const double hh = 0.5 * h;
+      const double sg = __builtin_fma(-4.0, hh - __builtin_floor(hh), 1.0);  // (-1)^h
+      g.s = (sg * x) * ps;
+      g.c = sg * pc;
+      g.kr = t * 6.283185307179586476925;
     } else {
       g.c = 1.0;
       g.s = 0.0;
@@ -117,7 +167,7 @@ struct SweepGeom {
   const typename Tr::coord* sx;  // [3][n]
   int64_t n;
   const int32_t* perm;
-  typename Tr::real kparam;      // F32: turns per quantum; F64: k
+  typename Tr::real kparam;      // F32: turns per quantum; F64: turns per unit length
   typename Tr::coord far;        // x offset of padding entries: farther than any near pair
   bool may_coincide;             // points of distinct boxes may coincide: mask every chunk
 };
@@ -144,7 +194,7 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
   } else {
     G.tx = P->tile_x64;
     G.sx = P->sx64;
-    G.kparam = P->k;
+    G.kparam = P->k / (2.0 * M_PI);
     G.far = 2.0 * P->max_sep + 1.0;  // near-pair differences stay below max_sep
   }
   return G;
