@@ -47,12 +47,13 @@ PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
 PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
 
 # Reverse pass (dq and dx together, FP32 Helmholtz), per pair: the geometry above
-# (3 differences, 3 for r^2, r, phase and reduction: 9 VALU + rsq, sin, cos), dq's
-# conj(G) g (2 + 4), u = conj(g_i) q_j + conj(g_j) q_i (8), (c + is)(ikr - 1) (3),
-# Re(G' u) (2), 1/r^3 (3) and the three dx multiply-adds (3): 34 VALU operations
-# plus 3 transcendentals = 40 issue slots.
-BWD_SLOTS_PER_PAIR = 34 + 2 * 3
-PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 982 Gpair/s
+# (3 differences, 3 for r^2, r, phase and reduction: 9 VALU + rsq, sin, cos), G =
+# (c + is)/r (2), dq's conj(G) g (4), u = conj(g_i) q_j + conj(g_j) q_i (8), the two
+# parts of (c + is)(ik - 1/r) (2), Re(G' u) (2), 1/r^2 and its product (2) and the
+# three dx multiply-adds (3): 32 VALU operations plus 3 transcendentals = 38 issue
+# slots.
+BWD_SLOTS_PER_PAIR = 32 + 2 * 3
+PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 1034 Gpair/s
 
 # Multi-RHS product: one complex multiply-add per (pair, right-hand side) = 8 real
 # flops on the FP32 matrix cores (dense FP32 MFMA peak 157.3 TFLOP/s).
@@ -203,7 +204,7 @@ def measure_backward(p2p, W, torch, reps):
         plan.close()
     out["roofline_f32"] = {"bound": "alu", "achieved": out["f32"]["gpairs_s"], "peak": round(PEAK_BWD_GPAIRS, 1),
                            "unit": "Gpair/s", "frac": round(out["f32"]["gpairs_s"] / PEAK_BWD_GPAIRS, 4),
-                           "work_per_pair": "34 VALU + 3 transcendental = %d issue slots" % BWD_SLOTS_PER_PAIR}
+                           "work_per_pair": "32 VALU + 3 transcendental = %d issue slots" % BWD_SLOTS_PER_PAIR}
     log("backward: f32 %.3f ms (%.1f Gpair/s, %.1f%% of its ALU roofline), f64 %.3f ms" % (
         out["f32"]["kernel_ms"], out["f32"]["gpairs_s"], 100 * out["roofline_f32"]["frac"], out["f64"]["kernel_ms"]))
     return out

@@ -25,6 +25,7 @@ struct BwdOp {
   double* __restrict__ gx;
   real q_scale;
   double x_scale;
+  real kw;  // the wavenumber in the geometry's units (FP32: radians per quantum)
 
   __device__ __forceinline__ void load_src(int32_t p, real* pay) const {
     const cplx q = qs[(int64_t)p * m + col], g = gs[(int64_t)p * m + col];
@@ -45,9 +46,10 @@ struct BwdOp {
   }
   template <bool HELM>
   __device__ __forceinline__ void pair(const typename Tr::Geo& G, const real* sp, const real* tp, real* acc) const {
+    // G = (c + i s) rinv
+    const real gr = G.c * G.rinv, gi = G.s * G.rinv;
     if (DQ) {
-      // conj(G) g_j, G = (c + i s) rinv
-      const real gr = G.c * G.rinv, gi = G.s * G.rinv;
+      // conj(G) g_j
       acc[0] = fma(gr, sp[2], acc[0]);
       acc[0] = fma(gi, sp[3], acc[0]);
       acc[1] = fma(gr, sp[3], acc[1]);
@@ -63,16 +65,17 @@ struct BwdOp {
       ui = fma(-tp[3], sp[0], ui);
       ui = fma(sp[2], tp[1], ui);
       ui = fma(-sp[3], tp[0], ui);
-      // 4 pi r^2 G' = (c + i s)(i k r - 1)
+      // 4 pi r G' = (c + i s)(i k r - 1) / r = (c + i s)(i k - rinv): since r rinv = 1,
+      // its parts are -(gr + s k) and c k - gi, with no product k r per pair
       real w;
       if (HELM) {
-        const real dr = -fma(G.s, G.kr, G.c);
-        const real di = fma(G.c, G.kr, -G.s);
+        const real dr = -fma(G.s, kw, gr);
+        const real di = fma(G.c, kw, -gi);
         w = fma(dr, ur, -(di * ui));
       } else {
-        w = -ur;
+        w = -gr * ur;
       }
-      w *= G.rinv * G.rinv * G.rinv;  // Re(G' u) / r, up to the scale
+      w *= G.rinv * G.rinv;  // Re(G' u) / r, up to the scale
       acc[OX + 0] = fma(w, G.dx, acc[OX + 0]);
       acc[OX + 1] = fma(w, G.dy, acc[OX + 1]);
       acc[OX + 2] = fma(w, G.dz, acc[OX + 2]);
@@ -125,8 +128,10 @@ static void launch_cols(p2p_plan_s* P, const SweepGeom<Tr>& G, void* gq, double*
   const double unit = f32 ? std::ldexp(1.0, -P->qexp) : 1.0;  // quantum -> length
   const real qsc = (real)(unit / (4.0 * M_PI));
   const double xsc = unit * unit / (4.0 * M_PI);
+  const real kw = (real)(P->k / unit);
   for (int c = 0; c < m; ++c) {
-    BwdOp<Tr, DQ, DX> op{(const cplx*)P->q_sorted, (const cplx*)P->g_sorted, m, c, P->perm, (cplx*)gq, gx, qsc, xsc};
+    BwdOp<Tr, DQ, DX> op{(const cplx*)P->q_sorted, (const cplx*)P->g_sorted, m, c, P->perm, (cplx*)gq, gx, qsc, xsc,
+                         kw};
     hipLaunchKernelGGL(kern, dim3(grid_for(G.nb, kWavesPerBlock)), dim3(kBlock), 0, s, G, op);
   }
 }

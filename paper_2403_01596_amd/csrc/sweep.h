@@ -33,14 +33,14 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 // ---------------------------------------------------------------------------
 // Pair geometry: given the target and source coordinates, the reciprocal distance
 // (zero when the distance is zero: the pair is skipped), and for the Helmholtz
-// kernel cos and sin of k r and the product k r.
+// kernel cos and sin of k r.
 struct F32 {
   using coord = int32_t;  // fixed point, units of 2^qexp, low 32 bits
   using real = float;
   using cplx = float2;
   static constexpr int K = 8;
   struct Geo {
-    float dx, dy, dz, rinv, c, s, kr;
+    float dx, dy, dz, rinv, c, s;
   };
   // k_turns: k * 2^qexp / (2 pi), the phase in turns per quantum of distance.
   // MASK: the pair may be at distance zero (then rinv = 0 and the term vanishes).
@@ -59,11 +59,9 @@ struct F32 {
       const float turns = (r2 * g.rinv) * k_turns;
       g.c = __builtin_amdgcn_cosf(turns);
       g.s = __builtin_amdgcn_sinf(turns);
-      g.kr = turns * 6.28318530717958647692f;
     } else {
       g.c = 1.0f;
       g.s = 0.0f;
-      g.kr = 0.0f;
     }
     return g;
   }
@@ -88,7 +86,7 @@ struct F64 {
   using cplx = double2;
   static constexpr int K = 4;
   struct Geo {
-    double dx, dy, dz, rinv, c, s, kr;
+    double dx, dy, dz, rinv, c, s;
   };
   // kt: k / (2 pi), the phase in turns per unit of distance.  Coordinates are the
   // caller's FP64 values, and the difference is formed exactly as in the
@@ -140,11 +138,9 @@ struct F64 {
       const double sg = __builtin_fma(-4.0, hh - __builtin_floor(hh), 1.0);  // (-1)^h
       g.s = (sg * x) * ps;
       g.c = sg * pc;
-      g.kr = t * 6.283185307179586476925;
     } else {
       g.c = 1.0;
       g.s = 0.0;
-      g.kr = 0.0;
     }
     return g;
   }
