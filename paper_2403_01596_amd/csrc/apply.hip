@@ -18,7 +18,7 @@ template <class Tr>
 struct FwdOp {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
-  static constexpr int NP = 2, NT = 0, NA = 2;
+  static constexpr int K = Tr::K, NP = 2, NT = 0, NA = 2;
   const cplx* __restrict__ qs;
   int m, col;
   const int32_t* __restrict__ perm;

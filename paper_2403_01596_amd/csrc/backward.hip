@@ -15,6 +15,7 @@ template <class Tr, bool DQ, bool DX>
 struct BwdOp {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
+  static constexpr int K = Tr::K;
   static constexpr int NP = 4, NT = DX ? 4 : 0, NA = (DQ ? 2 : 0) + (DX ? 3 : 0);
   static constexpr int OX = DQ ? 2 : 0;  // first dx accumulator
   const cplx* __restrict__ qs;

@@ -4,7 +4,7 @@
 // the adjacent boxes and evaluates the pair kernel.  Mapping on CDNA:
 //  - one wavefront per target box (boxes taken from a work list, largest first);
 //  - the 64 lanes hold 64 different sources of the box's neighbourhood, up to
-//    Tr::K chunks of 64 in registers at a time;
+//    K chunks of 64 in registers at a time (K chosen by the operation);
 //  - the box's targets are walked one at a time, wave-uniform, with their
 //    coordinates and payload in scalar registers;
 //  - every lane accumulates its sources' terms for the current target, and one
@@ -227,7 +227,7 @@ __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, 
 template <class Tr, class Op, bool CSR>
 struct SweepLds {
   typename Tr::real sums[Op::NA][kWave];
-  int32_t idx[CSR ? kWave * Tr::K : 1];
+  int32_t idx[CSR ? kWave * Op::K : 1];
 };
 
 // Which chunks of a group take the zero-distance mask: every chunk, the first
@@ -240,14 +240,14 @@ enum SweepMask { kMaskAll, kMaskFirst, kMaskNone };
 // All targets of the block [tb, te) against the group's chunks in registers.
 template <class Tr, class Op, bool HELM, int MODE, class LdsT>
 __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& op, LdsT& L,
-                                              const typename Tr::coord (&X)[Tr::K],
-                                              const typename Tr::coord (&Y)[Tr::K],
-                                              const typename Tr::coord (&Z)[Tr::K],
-                                              const typename Tr::real (&P)[Tr::K][Op::NP > 0 ? Op::NP : 1], int nch,
+                                              const typename Tr::coord (&X)[Op::K],
+                                              const typename Tr::coord (&Y)[Op::K],
+                                              const typename Tr::coord (&Z)[Op::K],
+                                              const typename Tr::real (&P)[Op::K][Op::NP > 0 ? Op::NP : 1], int nch,
                                               int32_t tb, int32_t te, bool first_group) {
   using real = typename Tr::real;
   using coord = typename Tr::coord;
-  constexpr int K = Tr::K;
+  constexpr int K = Op::K;
   constexpr int NT = Op::NT, NA = Op::NA;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t n = G.n;
@@ -304,6 +304,7 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
 }
 
 // The sweep.  Op supplies:
+//   K                     chunks of 64 sources held in registers per group
 //   NP, NT, NA            payload reals per source, per target, accumulators
 //   load_src(p, pay)      payload of the source at sorted position p
 //   load_tgt(t, pay)      payload of the target at sorted position t (uniform)
@@ -313,7 +314,7 @@ template <class Tr, class Op, bool HELM, bool CSR>
 __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, SweepLds<Tr, Op, CSR>& L) {
   using real = typename Tr::real;
   using coord = typename Tr::coord;
-  constexpr int K = Tr::K;
+  constexpr int K = Op::K;
   constexpr int NP = Op::NP, NA = Op::NA;
   const int lane = threadIdx.x & (kWave - 1);
   const int32_t w = uniform((int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
