@@ -323,6 +323,20 @@ __global__ void __launch_bounds__(kBlock) k_iota(int32_t* __restrict__ v, int64_
   if (e < n) v[e] = (int32_t)e;
 }
 
+// One pass of the sort over the digit at `shift`: keys kin -> kout, values vin
+// (null: the input positions) -> vout.  lim as for radix_sort below.
+template <typename KI, typename KO>
+static p2p_status radix_pass(const KI* kin, const int32_t* vin, KO* kout, int32_t* vout, int64_t n, int shift,
+                             uint32_t* hist, uint32_t* part, hipStream_t s, const int32_t* lim = nullptr) {
+  const int g = (int)grid_for(n, kRsTile);
+  hipLaunchKernelGGL(k_rs_hist<KI>, dim3(g), dim3(kBlock), 0, s, kin, n, lim, shift, hist, g);
+  hipLaunchKernelGGL(k_rs_rows, dim3(256), dim3(kBlock), 0, s, hist, g, part);
+  hipLaunchKernelGGL((k_rs_scatter<KI, KO>), dim3(g), dim3(kBlock), 0, s, kin, vin, kout, vout, n, lim, shift, hist,
+                     part, g);
+  P2P_HIP(hipGetLastError());
+  return P2P_OK;
+}
+
 // Sorts the keys k0[0..n) by their low `bits` bits; the stable order of the
 // positions lands in vals.  Workspace: kx (n u64), vx (n i32), hist (256 per tile
 // of kRsTile keys), part (256 digit totals).  lim (optional, device): the count of
@@ -1129,9 +1143,22 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
                        part);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
+  // The first radix pass does not depend on what the copy reports, so it is
+  // enqueued behind it and runs while the host waits: it assumes keys of at most
+  // 32 bits (narrowed on the way) and an odd number of passes (values into perm),
+  // which holds for 17-24 key bits; the other cases are put right below.
+  uint32_t* a32 = reinterpret_cast<uint32_t*>(k1);
+  uint32_t* b32 = a32 + n;
   DevStatus hs;
-  rc = read_status(status, &hs, s);
-  if (rc != P2P_OK) return rc;
+  {
+    StatusCopy copy;
+    rc = copy.start(status, s);
+    if (rc != P2P_OK) return rc;
+    rc = radix_pass<uint64_t, uint32_t>(k0, nullptr, a32, P->perm, n, 0, hist, partu, s);
+    if (rc != P2P_OK) return rc;
+    rc = copy.finish(&hs);
+    if (rc != P2P_OK) return rc;
+  }
   if (hs.st[ST_BAD_ID])
     return fail(P2P_ERR_RANGE, gspec ? "a coordinate is not finite or its box id falls outside [0, 2^21)"
                                      : "a box id falls outside [0, 2^21)");
@@ -1156,11 +1183,27 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     }
   }
 
-  // ---- 2. stable sort of the points by key, over the key bits in use
+  // ---- 2. stable sort of the points by key, over the key bits in use (8 per pass;
+  //         with no bits in use the first pass alone gives the identity order)
   const int bits = 3 * bit_length(hs.st[ST_ID_OR]);
   SortedKeys sk;
-  rc = radix_sort(k0, P->perm, k1, v1, n, bits, hist, partu, &sk, s);
-  if (rc != P2P_OK) return rc;
+  if (bits <= 32) {
+    const int passes = std::max(1, (bits + 7) / 8);
+    uint32_t *kc = a32, *ko = b32;
+    int32_t *vc = P->perm, *vo = v1;
+    for (int p = 1; p < passes; ++p) {
+      rc = radix_pass<uint32_t, uint32_t>(kc, vc, ko, vo, n, 8 * p, hist, partu, s);
+      if (rc != P2P_OK) return rc;
+      std::swap(kc, ko);
+      std::swap(vc, vo);
+    }
+    if (vc != P->perm) P2P_HIP(hipMemcpyAsync(P->perm, vc, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    sk.k32 = kc;
+    sk.k64 = nullptr;
+  } else {  // 64-bit keys: the speculative pass is discarded and the sort starts over
+    rc = radix_sort(k0, P->perm, k1, v1, n, bits, hist, partu, &sk, s);
+    if (rc != P2P_OK) return rc;
+  }
 
   // ---- 3. box table: runs of equal keys
   {
