@@ -151,15 +151,6 @@ static p2p_status scan_arrays(const ScanIO<T>& io, int arrays, int64_t n, hipStr
   return P2P_OK;
 }
 
-// out[0..n) = exclusive prefix of in; *total = sum (device pointer, may be null).
-// part: workspace of at least grid_for(n, kScanTile) elements.  in == out allowed.
-template <typename T>
-static p2p_status scan(const T* in, T* out, int64_t n, T* part, T* total, hipStream_t s,
-                       const int32_t* lim = nullptr) {
-  const ScanIO<T> io{{in, nullptr}, {out, nullptr}, {part, nullptr}, {total, nullptr}};
-  return scan_arrays<T>(io, 1, n, s, lim);
-}
-
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort of (key, i32 value), 8 bits per pass.  Per pass: digit
 // counts per tile, a scan of each digit's row of tile counts (one workgroup per
