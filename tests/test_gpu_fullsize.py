@@ -6,10 +6,15 @@ FP64 oracle.
 - the multi-right-hand-side batch (1M sphere points plus 16 uneven instances,
   64 columns each) in one tuned launch: sampled rows of every instance;
 - the 500k-point cube's reverse pass (dq and dx), FP32 and FP64, against the
-  oracle's full reverse pass.
+  oracle's full reverse pass;
+- 2^25 points in the unit cube on a 100^3 grid (a million boxes, a replicated
+  list of about 900M entries, close to the 2^31 limit of the 32-bit list
+  offsets), both layouts, FP32: tables against the oracle's, sampled rows.
 
 Bars: relative L2 error <= 1e-5 (FP32 path), <= 1e-12 (FP64 path).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -89,3 +94,26 @@ def test_cube_500k_reverse_pass():
         print("  %s dq %.3e dx %.3e" % (dtype, e_q, e_x), flush=True)
         assert e_q <= TOL[dtype] and e_x <= TOL[dtype]
         P.close()
+
+
+def test_cube_33m_both_layouts():
+    n, grid = 1 << 25, 100
+    k = 2 * math.pi * grid / 4  # boxes of a quarter wavelength
+    inst = W.cube(n, grid, k, seed=12, dtype=np.complex64)
+    print("cube 2^25 generated", flush=True)
+    orc = oracle.Plan(inst.ids)
+    rows = np.random.default_rng(12).choice(n, 400, replace=False)
+    yref = orc.apply_rows(inst.xyz, k, inst.q, rows)
+    xyz, ids, q = dev(inst.xyz, torch.float64), dev(inst.ids, torch.int32), dev(inst.q)
+    for layout in ("csr", "tiles"):
+        P = p2p.Plan(xyz, ids, k, dtype=torch.complex64, layout=layout)
+        info = P.info()
+        assert info["n_boxes"] == orc.n_boxes and info["n_nbr"] == orc.n_nbr
+        y = P.apply(q)
+        torch.cuda.synchronize()
+        err = rel_l2(y.cpu().numpy()[rows], yref)
+        print("  %s: %d boxes, list %d entries, rel L2 on sampled rows %.3e" % (
+            layout, info["n_boxes"], info["tile_entries"], err), flush=True)
+        assert err <= TOL[torch.complex64]
+        P.close()
+        del y
