@@ -55,6 +55,15 @@ PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
 BWD_SLOTS_PER_PAIR = 32 + 2 * 3
 PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 1034 Gpair/s
 
+# FP64 sweep, per pair: 3 differences, 3 for r^2, the 1/r refinement (5), r and the
+# phase in turns (2), the half-turn reduction (3), x^2, x^4, x^8 (3), the sine and
+# cosine polynomials (20) and the sine's factor x (1), the sign of an odd half
+# turn (4) and its application (2), G (2) and the complex multiply-add (4): 52 FP64
+# VALU operations at one slot each (FP64 FMA measured at 49-53 lanes per clock per
+# CU) plus v_rsq_f64 at 16 lanes per clock, 4 slots: 56 issue slots.
+F64_SLOTS_PER_PAIR = 52 + 4
+PEAK_F64_GPAIRS = PEAK_SLOTS / F64_SLOTS_PER_PAIR / 1e9   # 702 Gpair/s
+
 # Multi-RHS product: one complex multiply-add per (pair, right-hand side) = 8 real
 # flops on the FP32 matrix cores (dense FP32 MFMA peak 157.3 TFLOP/s).
 FLOPS_PER_PAIR_RHS = 8
@@ -451,7 +460,12 @@ def main():
                   "f32_%s_ms" % args.layout: round(apply32_ms, 4), "f32_%s_ms" % other: round(apply_o_ms, 4),
                   "f64_%s_ms" % args.layout: round(apply64_ms, 4),
                   "sweep_ms": {"f32_" + args.layout: round(sweep32_ms, 4), "f32_" + other: round(sweep_o_ms, 4),
-                               "f64_" + args.layout: round(sweep64_ms, 4)}},
+                               "f64_" + args.layout: round(sweep64_ms, 4)},
+                  "roofline_f64": {"bound": "alu", "achieved": round(n_pairs / sweep64_ms / 1e6, 2),
+                                   "peak": round(PEAK_F64_GPAIRS, 1), "unit": "Gpair/s",
+                                   "frac": round(n_pairs / sweep64_ms / 1e6 / PEAK_F64_GPAIRS, 4),
+                                   "work_per_pair": "52 FP64 VALU + v_rsq_f64 (4) = %d issue slots"
+                                                    % F64_SLOTS_PER_PAIR}},
         "plan_ms": round(plan_s * 1e3, 3),
         "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "box_ids_call_ms": round(box_ids_ms, 4),
