@@ -46,14 +46,20 @@ def test_apply_matches_oracle(case, dtype, layout):
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout", ["tiles", "csr"])
-def test_multiple_rhs(dtype, layout):
+@pytest.mark.parametrize("m", [3, 8, 15])
+def test_multiple_rhs(dtype, layout, m):
+    # columns go in launches of 8, 4, 2 and 1 (15 = 8 + 4 + 2 + 1)
     inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=11)
-    q = strengths(inst.n, 3, dtype, seed=5)
-    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=3)
+    q = strengths(inst.n, m, dtype, seed=5)
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=m)
     y = gpu_apply(P, q, dtype)
     yref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, q)
-    for c in range(3):
-        assert rel_l2(y[:, c], yref[:, c]) <= TOL[dtype]
+    for c in range(m):
+        assert rel_l2(y[:, c], yref[:, c]) <= TOL[dtype], c
+    # the same columns one at a time give the same numbers up to rounding
+    P1 = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout)
+    y1 = np.stack([gpu_apply(P1, np.ascontiguousarray(q[:, c:c + 1]), dtype)[:, 0] for c in range(m)], axis=1)
+    assert rel_l2(y, y1) <= TOL[dtype]
 
 
 def test_deterministic_and_layouts_agree():
