@@ -11,13 +11,17 @@
 
 namespace p2p {
 
-template <class Tr, bool DQ, bool DX>
+// M columns per launch: the kernel value, G' and the geometry are formed once per
+// pair and serve every column; dx sums over the columns in one accumulator set.
+// Chunks per group: the precision's count up to 2 columns, half of it for 4
+// (measured on the 500k cube).
+template <class Tr, bool DQ, bool DX, int M = 1>
 struct BwdOp {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
-  static constexpr int K = Tr::K;
-  static constexpr int NP = 4, NT = DX ? 4 : 0, NA = (DQ ? 2 : 0) + (DX ? 3 : 0);
-  static constexpr int OX = DQ ? 2 : 0;  // first dx accumulator
+  static constexpr int K = M <= 2 ? Tr::K : Tr::K / 2;
+  static constexpr int NP = 4 * M, NT = DX ? 4 * M : 0, NA = (DQ ? 2 * M : 0) + (DX ? 3 : 0);
+  static constexpr int OX = DQ ? 2 * M : 0;  // first dx accumulator
   const cplx* __restrict__ qs;
   const cplx* __restrict__ gs;
   int m, col;
@@ -29,20 +33,26 @@ struct BwdOp {
   real kw;  // the wavenumber in the geometry's units (FP32: radians per quantum)
 
   __device__ __forceinline__ void load_src(int32_t p, real* pay) const {
-    const cplx q = qs[(int64_t)p * m + col], g = gs[(int64_t)p * m + col];
-    pay[0] = q.x;
-    pay[1] = q.y;
-    pay[2] = g.x;
-    pay[3] = g.y;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const cplx q = qs[(int64_t)p * m + col + c], g = gs[(int64_t)p * m + col + c];
+      pay[4 * c] = q.x;
+      pay[4 * c + 1] = q.y;
+      pay[4 * c + 2] = g.x;
+      pay[4 * c + 3] = g.y;
+    }
   }
   __device__ __forceinline__ void load_tgt(int32_t t, real* tp) const {
     if (DX) {
-      const real* q = reinterpret_cast<const real*>(qs + (int64_t)t * m + col);
-      const real* g = reinterpret_cast<const real*>(gs + (int64_t)t * m + col);
-      tp[0] = ld_uniform(q);
-      tp[1] = ld_uniform(q + 1);
-      tp[2] = ld_uniform(g);
-      tp[3] = ld_uniform(g + 1);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const real* q = reinterpret_cast<const real*>(qs + (int64_t)t * m + col + c);
+        const real* g = reinterpret_cast<const real*>(gs + (int64_t)t * m + col + c);
+        tp[4 * c] = ld_uniform(q);
+        tp[4 * c + 1] = ld_uniform(q + 1);
+        tp[4 * c + 2] = ld_uniform(g);
+        tp[4 * c + 3] = ld_uniform(g + 1);
+      }
     }
   }
   template <bool HELM>
@@ -51,32 +61,43 @@ struct BwdOp {
     const real gr = G.c * G.rinv, gi = G.s * G.rinv;
     if (DQ) {
       // conj(G) g_j
-      acc[0] = fma(gr, sp[2], acc[0]);
-      acc[0] = fma(gi, sp[3], acc[0]);
-      acc[1] = fma(gr, sp[3], acc[1]);
-      acc[1] = fma(-gi, sp[2], acc[1]);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const real* p = sp + 4 * c;
+        acc[2 * c] = fma(gr, p[2], acc[2 * c]);
+        acc[2 * c] = fma(gi, p[3], acc[2 * c]);
+        acc[2 * c + 1] = fma(gr, p[3], acc[2 * c + 1]);
+        acc[2 * c + 1] = fma(-gi, p[2], acc[2 * c + 1]);
+      }
     }
     if (DX) {
-      // u = conj(g_i) q_j + conj(g_j) q_i
-      real ur = tp[2] * sp[0];
-      ur = fma(tp[3], sp[1], ur);
-      ur = fma(sp[2], tp[0], ur);
-      ur = fma(sp[3], tp[1], ur);
-      real ui = tp[2] * sp[1];
-      ui = fma(-tp[3], sp[0], ui);
-      ui = fma(sp[2], tp[1], ui);
-      ui = fma(-sp[3], tp[0], ui);
       // 4 pi r G' = (c + i s)(i k r - 1) / r = (c + i s)(i k - rinv): since r rinv = 1,
       // its parts are -(gr + s k) and c k - gi, with no product k r per pair
-      real w;
+      real dr, di;
       if (HELM) {
-        const real dr = -fma(G.s, kw, gr);
-        const real di = fma(G.c, kw, -gi);
-        w = fma(dr, ur, -(di * ui));
+        dr = -fma(G.s, kw, gr);
+        di = fma(G.c, kw, -gi);
       } else {
-        w = -gr * ur;
+        dr = -gr;
+        di = real(0);
       }
-      w *= G.rinv * G.rinv;  // Re(G' u) / r, up to the scale
+      real w = real(0);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const real *p = sp + 4 * c, *t = tp + 4 * c;
+        // u = conj(g_i) q_j + conj(g_j) q_i
+        real ur = t[2] * p[0];
+        ur = fma(t[3], p[1], ur);
+        ur = fma(p[2], t[0], ur);
+        ur = fma(p[3], t[1], ur);
+        real ui = t[2] * p[1];
+        ui = fma(-t[3], p[0], ui);
+        ui = fma(p[2], t[1], ui);
+        ui = fma(-p[3], t[0], ui);
+        w = fma(dr, ur, w);
+        if (HELM) w = fma(-di, ui, w);
+      }
+      w *= G.rinv * G.rinv;  // sum over the columns of Re(G' u) / r, up to the scale
       acc[OX + 0] = fma(w, G.dx, acc[OX + 0]);
       acc[OX + 1] = fma(w, G.dy, acc[OX + 1]);
       acc[OX + 2] = fma(w, G.dz, acc[OX + 2]);
@@ -85,10 +106,13 @@ struct BwdOp {
   __device__ __forceinline__ void store(int32_t t, const real* a) const {
     const int64_t i = perm[t];
     if (DQ) {
-      cplx v;
-      v.x = a[0] * q_scale;
-      v.y = a[1] * q_scale;
-      gq[i * m + col] = v;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        cplx v;
+        v.x = a[2 * c] * q_scale;
+        v.y = a[2 * c + 1] * q_scale;
+        gq[i * m + col + c] = v;
+      }
     }
     if (DX) {
       for (int d = 0; d < 3; ++d) {
@@ -99,10 +123,10 @@ struct BwdOp {
   }
 };
 
-template <class Tr, bool HELM, bool CSR, bool DQ, bool DX>
-__global__ void __launch_bounds__(kBlock) k_backward(SweepGeom<Tr> G, BwdOp<Tr, DQ, DX> op) {
-  __shared__ SweepLds<Tr, BwdOp<Tr, DQ, DX>, CSR> lds[kWavesPerBlock];
-  sweep<Tr, BwdOp<Tr, DQ, DX>, HELM, CSR>(G, op, lds[threadIdx.x / kWave]);
+template <class Tr, bool HELM, bool CSR, bool DQ, bool DX, int M = 1>
+__global__ void __launch_bounds__(kBlock) k_backward(SweepGeom<Tr> G, BwdOp<Tr, DQ, DX, M> op) {
+  __shared__ SweepLds<Tr, BwdOp<Tr, DQ, DX, M>, CSR> lds[kWavesPerBlock];
+  sweep<Tr, BwdOp<Tr, DQ, DX, M>, HELM, CSR>(G, op, lds[threadIdx.x / kWave]);
 }
 
 template <typename C>
@@ -118,22 +142,39 @@ __global__ void __launch_bounds__(kBlock) k_gather_rows2(const C* __restrict__ q
   gs[e] = g[src];
 }
 
-template <class Tr, bool DQ, bool DX>
-static void launch_cols(p2p_plan_s* P, const SweepGeom<Tr>& G, void* gq, double* gx, int m, hipStream_t s) {
+template <class Tr, bool DQ, bool DX, int M>
+static void launch_block(p2p_plan_s* P, const SweepGeom<Tr>& G, void* gq, double* gx, int m, int col,
+                         hipStream_t s) {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
   const bool helm = P->k != 0.0, csr = P->layout == P2P_LAYOUT_CSR;
-  auto kern = helm ? (csr ? k_backward<Tr, true, true, DQ, DX> : k_backward<Tr, true, false, DQ, DX>)
-                   : (csr ? k_backward<Tr, false, true, DQ, DX> : k_backward<Tr, false, false, DQ, DX>);
+  auto kern = helm ? (csr ? k_backward<Tr, true, true, DQ, DX, M> : k_backward<Tr, true, false, DQ, DX, M>)
+                   : (csr ? k_backward<Tr, false, true, DQ, DX, M> : k_backward<Tr, false, false, DQ, DX, M>);
   const bool f32 = P->precision == P2P_C64;
   const double unit = f32 ? std::ldexp(1.0, -P->qexp) : 1.0;  // quantum -> length
   const real qsc = (real)(unit / (4.0 * M_PI));
   const double xsc = unit * unit / (4.0 * M_PI);
   const real kw = (real)(P->k / unit);
-  for (int c = 0; c < m; ++c) {
-    BwdOp<Tr, DQ, DX> op{(const cplx*)P->q_sorted, (const cplx*)P->g_sorted, m, c, P->perm, (cplx*)gq, gx, qsc, xsc,
-                         kw};
-    hipLaunchKernelGGL(kern, dim3(grid_for(G.nb, kWavesPerBlock)), dim3(kBlock), 0, s, G, op);
+  BwdOp<Tr, DQ, DX, M> op{(const cplx*)P->q_sorted, (const cplx*)P->g_sorted, m, col, P->perm, (cplx*)gq, gx, qsc,
+                          xsc, kw};
+  hipLaunchKernelGGL(kern, dim3(grid_for(G.nb, kWavesPerBlock)), dim3(kBlock), 0, s, G, op);
+}
+
+// columns in launches of 4, 2 and 1
+template <class Tr, bool DQ, bool DX>
+static void launch_cols(p2p_plan_s* P, const SweepGeom<Tr>& G, void* gq, double* gx, int m, hipStream_t s) {
+  for (int c = 0; c < m;) {
+    const int left = m - c;
+    if (left >= 4) {
+      launch_block<Tr, DQ, DX, 4>(P, G, gq, gx, m, c, s);
+      c += 4;
+    } else if (left >= 2) {
+      launch_block<Tr, DQ, DX, 2>(P, G, gq, gx, m, c, s);
+      c += 2;
+    } else {
+      launch_block<Tr, DQ, DX, 1>(P, G, gq, gx, m, c, s);
+      c += 1;
+    }
   }
 }
 

@@ -71,13 +71,22 @@ def test_autograd_function(dtype):
     assert rel_l2(xyz.grad.cpu().numpy(), dx_ref) <= TOL[dtype]
 
 
-def test_multi_rhs_backward():
-    inst = W.sphere(20000, 32, 2 * math.pi * 8, seed=46, m=2, dtype=np.complex128)
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+@pytest.mark.parametrize("m", [2, 7])
+def test_multi_rhs_backward(dtype, layout, m):
+    # columns go in launches of 4, 2 and 1 (7 = 4 + 2 + 1); dx sums over all of them
+    npd = np.complex128 if dtype == torch.complex128 else np.complex64
+    inst = W.sphere(20000, 32, 2 * math.pi * 8, seed=46, m=m, dtype=np.complex128)
     orc = oracle.Plan(inst.ids)
-    y = orc.apply(inst.xyz, inst.k, inst.q)
-    dq_ref, dx_ref = orc.backward(inst.xyz, inst.k, inst.q, 2 * y)
-    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=torch.complex128, max_rhs=2)
-    dq, dx = P.backward(dev(inst.q), dev(2 * y))
-    torch.cuda.synchronize()
-    assert rel_l2(dq.cpu().numpy(), dq_ref) <= 1e-12
-    assert rel_l2(dx.cpu().numpy(), dx_ref) <= 1e-12
+    q = inst.q.astype(npd)
+    g = (2 * orc.apply(inst.xyz, inst.k, q)).astype(npd)
+    dq_ref, dx_ref = orc.backward(inst.xyz, inst.k, q, g)
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=m)
+    for want_dq, want_dx in ((True, True), (True, False), (False, True)):
+        dq, dx = P.backward(dev(q), dev(g), want_dq=want_dq, want_dx=want_dx)
+        torch.cuda.synchronize()
+        if want_dq:
+            assert rel_l2(dq.cpu().numpy(), dq_ref) <= TOL[dtype]
+        if want_dx:
+            assert rel_l2(dx.cpu().numpy(), dx_ref) <= TOL[dtype]
