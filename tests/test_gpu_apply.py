@@ -114,14 +114,16 @@ def test_sphere_2m_sampled_rows():
 
 
 @pytest.mark.parametrize("layout", ["csr", "tiles"])
-def test_graph_capture_of_apply_and_backward(layout):
+@pytest.mark.parametrize("m", [1, 7])
+def test_graph_capture_of_apply_and_backward(layout, m):
     """p2p_apply and p2p_apply_backward allocate nothing and do not synchronise, so a
     HIP graph can hold them: three replays, with eager work and new inputs between
-    them, each equal bitwise to an eager call on the same inputs."""
+    them, each equal bitwise to an eager call on the same inputs.  Seven columns take
+    launches of 4, 2 and 1 columns in both passes."""
     inst = W.sphere(40000, 32, 2 * math.pi * 10, seed=77)
-    P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout)
-    q = dev(inst.q.astype(np.complex64))
-    g = dev(W.strengths(inst.n, 1, np.random.default_rng(3), np.complex64))
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout, max_rhs=m)
+    q = dev(W.strengths(inst.n, m, np.random.default_rng(4), np.complex64))
+    g = dev(W.strengths(inst.n, m, np.random.default_rng(3), np.complex64))
     y = torch.empty_like(q)
     dq = torch.empty_like(q)
     dx = torch.empty((inst.n, 3), dtype=torch.float64, device="cuda")
@@ -130,8 +132,8 @@ def test_graph_capture_of_apply_and_backward(layout):
     def calls():
         s = torch.cuda.current_stream().cuda_stream
         p = lambda t: ctypes.c_void_p(t.data_ptr())
-        assert lib.p2p_apply(P.handle, p(q), p(y), 1, 1, ctypes.c_void_p(s)) == 0
-        assert lib.p2p_apply_backward(P.handle, p(q), p(g), p(dq), p(dx), 1, 1, ctypes.c_void_p(s)) == 0
+        assert lib.p2p_apply(P.handle, p(q), p(y), m, 1, ctypes.c_void_p(s)) == 0
+        assert lib.p2p_apply_backward(P.handle, p(q), p(g), p(dq), p(dx), m, 1, ctypes.c_void_p(s)) == 0
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
