@@ -130,7 +130,9 @@ p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int
     (void)hipGetLastError();
     e0 = e1 = nullptr;
   }
-  p2p_status rc = run(b, io, b->width, b->wpb, s, e0, e1);
+  // a call with at most 32 right-hand sides fills 32-column items and would leave
+  // at least half of every 64-column item idle
+  p2p_status rc = run(b, io, m <= 32 ? 32 : b->width, b->wpb, s, e0, e1);
   if (e0) sink->emplace_back(e0, e1);
   return rc;
 }

@@ -46,9 +46,11 @@ def test_apply_matches_oracle(case, dtype, layout):
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout", ["tiles", "csr"])
-@pytest.mark.parametrize("m", [3, 8, 15])
+@pytest.mark.parametrize("m", [3, 7, 11, 15])
 def test_multiple_rhs(dtype, layout, m):
-    # columns go in launches of 8, 4, 2 and 1 (15 = 8 + 4 + 2 + 1)
+    # below 12 columns (and for FP64 plans) the columns go in launches of 8, 4, 2 and 1
+    # (7 = 4 + 2 + 1, 11 = 8 + 2 + 1, 15 = 8 + 4 + 2 + 1); complex64 plans take 15 to the
+    # matrix cores
     inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=11)
     q = strengths(inst.n, m, dtype, seed=5)
     P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=m)

@@ -23,11 +23,11 @@ def strengths(n, m, seed):
 
 
 @pytest.mark.parametrize("layout", ["csr", "tiles"])
-@pytest.mark.parametrize("m", [16, 20, 64, 71])
+@pytest.mark.parametrize("m", [12, 16, 20, 64, 71])
 def test_single_plan_many_rhs(layout, m):
     inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=61)
     q = strengths(inst.n, m, 7)
-    P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout, max_rhs=max(m, 16))
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout, max_rhs=m)
     y = P.apply(dev(q))
     torch.cuda.synchronize()
     yref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, q)
