@@ -878,6 +878,14 @@ __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict_
   key[T] = (uint64_t)(255 - b);
 }
 
+// Lane j's value of a double (wave-uniform j).
+__device__ __forceinline__ double lane_read(double v, int j) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), j);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Zero-distance pairs (self pairs included), FP64 coordinates, one wavefront per
 // box; one partial sum per workgroup.  self_only: points of distinct boxes cannot
 // coincide (their bounding boxes do not meet), so only the box's own points are
@@ -892,13 +900,26 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
   const int lane = threadIdx.x & (kWave - 1);
   uint32_t z = 0;
   if (T < nb) {
+    // up to 64 targets and 64 sources in registers at a time, lane l holding one of
+    // each; the targets are walked with lane reads, so the inner loop touches no
+    // memory.  Lanes past a chunk's end hold NaN, which equals nothing.
     const int32_t e0 = self_only ? 0 : nbr_start[T], e1 = self_only ? 1 : nbr_start[T + 1];
-    for (int32_t t = box_start[T]; t < box_start[T + 1]; ++t) {
-      const double x = sx[t], y = sx[n + t], w = sx[2 * n + t];
+    const int32_t b0 = box_start[T], b1 = box_start[T + 1];
+    for (int32_t tb = b0; tb < b1; tb += kWave) {
+      const int nt = min(kWave, b1 - tb);
+      const bool tl = lane < nt;
+      const double tx = tl ? sx[tb + lane] : NAN, ty = tl ? sx[n + tb + lane] : NAN,
+                   tz = tl ? sx[2 * n + tb + lane] : NAN;
       for (int32_t e = e0; e < e1; ++e) {
         const int32_t S = self_only ? (int32_t)T : nbr_idx[e];
-        for (int32_t p = box_start[S] + lane; p < box_start[S + 1]; p += kWave)
-          z += (sx[p] == x && sx[n + p] == y && sx[2 * n + p] == w) ? 1 : 0;
+        const int32_t s0 = box_start[S], s1 = box_start[S + 1];
+        for (int32_t sb = s0; sb < s1; sb += kWave) {
+          const bool sl = lane < s1 - sb;
+          const double qx = sl ? sx[sb + lane] : NAN, qy = sl ? sx[n + sb + lane] : NAN,
+                       qz = sl ? sx[2 * n + sb + lane] : NAN;
+          for (int j = 0; j < nt; ++j)
+            z += (qx == lane_read(tx, j) && qy == lane_read(ty, j) && qz == lane_read(tz, j)) ? 1 : 0;
+        }
       }
     }
   }
