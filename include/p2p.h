@@ -161,9 +161,9 @@ p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls);
  * [n_i, nrhs] complex64 in plan i's point order; one kernel launch that reads the
  * strengths in that order, no allocation, no scratch memory and no
  * synchronisation (capturable in a HIP graph, replayable with the same pointers).
- * Plans created with max_rhs >= 12 use the same path from p2p_apply when
- * nrhs >= 12.  A call with nrhs <= 32 uses 32 columns per work item whatever
- * the autotuner chose. */
+ * Plans created with max_rhs >= 6 use the same path from p2p_apply when
+ * nrhs >= 6.  A call with nrhs <= 16 (<= 32) uses 16 (32) columns per work item,
+ * whatever the autotuner chose. */
 typedef struct p2p_batch_s* p2p_batch;
 p2p_status p2p_batch_create(const p2p_plan* plans, int32_t count, int32_t nrhs, p2p_batch* out);
 p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y, void* stream);

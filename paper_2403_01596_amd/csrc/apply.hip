@@ -121,14 +121,21 @@ static p2p_status run_apply(p2p_plan_s* P, const void* q, void* y, int m, hipStr
   const real sc = (real)fwd_scale<Tr>(P);
   SweepTimer timer(P, s);
   timer.start();
-  // columns in blocks of 8, 4, 2 and 1, one launch per block
+  // columns in blocks of 8 (FP64 only: complex64 plans serve that many columns on
+  // the matrix cores), 4, 2 and 1, one launch per block
   const dim3 grid(grid_for(G.nb, kWavesPerBlock)), block(kBlock);
+  constexpr bool kBlocks8 = std::is_same<Tr, F64>::value;
   for (int c = 0; c < m;) {
     const int left = m - c;
-    if (left >= 8) {
-      launch_cols<Tr, 8>(G, FwdOp<Tr, 8>{(const cplx*)P->q_sorted, m, c, P->perm, (cplx*)y, sc}, helm, csr, grid, s);
-      c += 8;
-    } else if (left >= 4) {
+    if constexpr (kBlocks8) {
+      if (left >= 8) {
+        launch_cols<Tr, 8>(G, FwdOp<Tr, 8>{(const cplx*)P->q_sorted, m, c, P->perm, (cplx*)y, sc}, helm, csr, grid,
+                           s);
+        c += 8;
+        continue;
+      }
+    }
+    if (left >= 4) {
       launch_cols<Tr, 4>(G, FwdOp<Tr, 4>{(const cplx*)P->q_sorted, m, c, P->perm, (cplx*)y, sc}, helm, csr, grid, s);
       c += 4;
     } else if (left >= 2) {

@@ -15,7 +15,7 @@ struct p2p_batch_s {
   int count, m;
   std::vector<p2p_plan_s*> plans;
   void* mem;                   // device: descriptors and both item lists
-  p2p::MrhsSetup set64, set32;  // items for 64 and for 32 right-hand sides per item
+  p2p::MrhsSetup set64, set32, set16;  // items for 64, 32 and 16 right-hand sides per item
   int width, wpb;              // launch shape
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
@@ -70,17 +70,20 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
     desc[i] = make_desc(plans[i]);
     helm = helm || plans[i]->k != 0.0;
   }
-  std::vector<int4> it64, it32;
-  XcdSplit sp64, sp32;
+  std::vector<int4> it64, it32, it16;
+  XcdSplit sp64, sp32, sp16;
   p2p_status rc = build_items(b->plans, m, 64, it64, sp64);
   if (rc == P2P_OK) rc = build_items(b->plans, m, 32, it32, sp32);
+  if (rc == P2P_OK) rc = build_items(b->plans, m, 16, it16, sp16);
   if (rc != P2P_OK) {
     batch_free(b);
     return rc;
   }
-  const size_t bd = sizeof(InstDesc) * count, b64 = sizeof(int4) * it64.size(), b32 = sizeof(int4) * it32.size();
-  const size_t off64 = (bd + 255) & ~size_t(255), off32 = (off64 + b64 + 255) & ~size_t(255);
-  b->mem = dmem_alloc(off32 + b32 + 16);
+  const size_t bd = sizeof(InstDesc) * count, b64 = sizeof(int4) * it64.size(), b32 = sizeof(int4) * it32.size(),
+               b16 = sizeof(int4) * it16.size();
+  const size_t off64 = (bd + 255) & ~size_t(255), off32 = (off64 + b64 + 255) & ~size_t(255),
+               off16 = (off32 + b32 + 255) & ~size_t(255);
+  b->mem = dmem_alloc(off16 + b16 + 16);
   if (!b->mem) {
     batch_free(b);
     return fail(P2P_ERR_NOMEM, "device allocation for the batch failed");
@@ -89,6 +92,7 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
   hipError_t e = hipMemcpy(base, desc.data(), bd, hipMemcpyHostToDevice);
   if (e == hipSuccess && b64) e = hipMemcpy(base + off64, it64.data(), b64, hipMemcpyHostToDevice);
   if (e == hipSuccess && b32) e = hipMemcpy(base + off32, it32.data(), b32, hipMemcpyHostToDevice);
+  if (e == hipSuccess && b16) e = hipMemcpy(base + off16, it16.data(), b16, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     batch_free(b);
     return hip_fail(e, "hipMemcpy (batch tables)");
@@ -98,6 +102,7 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
   for (int i = 0; i < count; ++i) small = small && plans[i]->n * (int64_t)m * 8 < (int64_t(1) << 32);
   b->set64 = MrhsSetup{(InstDesc*)base, (int4*)(base + off64), (int64_t)it64.size(), sp64, helm, csr, small};
   b->set32 = MrhsSetup{(InstDesc*)base, (int4*)(base + off32), (int64_t)it32.size(), sp32, helm, csr, small};
+  b->set16 = MrhsSetup{(InstDesc*)base, (int4*)(base + off16), (int64_t)it16.size(), sp16, helm, csr, small};
   *out = b;
   return P2P_OK;
 }
@@ -116,7 +121,7 @@ static BatchIO make_io(const p2p_batch_s* b, const void* const* q, void* const* 
 
 static p2p_status run(p2p_batch_s* b, const BatchIO& io, int width, int wpb, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  return launch_mrhs(width == 64 ? b->set64 : b->set32, io, width, wpb, s, e0, e1);
+  return launch_mrhs(width == 64 ? b->set64 : (width == 32 ? b->set32 : b->set16), io, width, wpb, s, e0, e1);
 }
 
 p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int m, hipStream_t s, bool timing,
@@ -130,9 +135,9 @@ p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int
     (void)hipGetLastError();
     e0 = e1 = nullptr;
   }
-  // a call with at most 32 right-hand sides fills 32-column items and would leave
-  // at least half of every 64-column item idle
-  p2p_status rc = run(b, io, m <= 32 ? 32 : b->width, b->wpb, s, e0, e1);
+  // a call with at most 16 (32) right-hand sides fills 16-column (32-column) items
+  // and would leave at least half of every wider item idle
+  p2p_status rc = run(b, io, m <= 16 ? 16 : (m <= 32 ? 32 : b->width), b->wpb, s, e0, e1);
   if (e0) sink->emplace_back(e0, e1);
   return rc;
 }

@@ -9,7 +9,7 @@
 namespace p2p {
 
 constexpr int kMaxBatch = 32;  // instances per batch (their pointers travel as kernel arguments)
-constexpr int kMrhsMin = 12;   // right-hand sides from which p2p_apply uses the matrix cores
+constexpr int kMrhsMin = 6;   // right-hand sides from which p2p_apply uses the matrix cores
 
 // Geometry of one instance, in device memory, read by the batched kernels.
 struct InstDesc {

@@ -340,8 +340,10 @@ p2p_status launch_mrhs(const MrhsSetup& S, const BatchIO& io, int width, int wpb
   } while (0)
   if (width == 64) {
     if (S.helm) P2P_MRHS_C(4, true); else P2P_MRHS_C(4, false);
-  } else {
+  } else if (width == 32) {
     if (S.helm) P2P_MRHS_C(2, true); else P2P_MRHS_C(2, false);
+  } else {
+    if (S.helm) P2P_MRHS_C(1, true); else P2P_MRHS_C(1, false);
   }
 #undef P2P_MRHS_C
 #undef P2P_MRHS_O

@@ -46,11 +46,11 @@ def test_apply_matches_oracle(case, dtype, layout):
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["f64", "f32"])
 @pytest.mark.parametrize("layout", ["tiles", "csr"])
-@pytest.mark.parametrize("m", [3, 7, 11, 15])
+@pytest.mark.parametrize("m", [3, 5, 7, 11, 15])
 def test_multiple_rhs(dtype, layout, m):
-    # below 12 columns (and for FP64 plans) the columns go in launches of 8, 4, 2 and 1
-    # (7 = 4 + 2 + 1, 11 = 8 + 2 + 1, 15 = 8 + 4 + 2 + 1); complex64 plans take 15 to the
-    # matrix cores
+    # complex64 plans: up to 5 columns in launches of 4, 2 and 1 (3 = 2 + 1, 5 = 4 + 1), from 6
+    # columns on the matrix cores; complex128 plans: launches of 8, 4, 2 and 1 (7 = 4 + 2 + 1,
+    # 11 = 8 + 2 + 1, 15 = 8 + 4 + 2 + 1)
     inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=11)
     q = strengths(inst.n, m, dtype, seed=5)
     P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=dtype, layout=layout, max_rhs=m)
@@ -116,12 +116,13 @@ def test_sphere_2m_sampled_rows():
 
 
 @pytest.mark.parametrize("layout", ["csr", "tiles"])
-@pytest.mark.parametrize("m", [1, 7])
+@pytest.mark.parametrize("m", [1, 5, 7])
 def test_graph_capture_of_apply_and_backward(layout, m):
     """p2p_apply and p2p_apply_backward allocate nothing and do not synchronise, so a
     HIP graph can hold them: three replays, with eager work and new inputs between
-    them, each equal bitwise to an eager call on the same inputs.  Seven columns take
-    launches of 4, 2 and 1 columns in both passes."""
+    them, each equal bitwise to an eager call on the same inputs.  Five columns take
+    launches of 4 and 1 columns in both passes; seven take the matrix cores forward
+    and launches of 4, 2 and 1 columns backward."""
     inst = W.sphere(40000, 32, 2 * math.pi * 10, seed=77)
     P = gpu_plan(inst.xyz, inst.ids, inst.k, layout=layout, max_rhs=m)
     q = dev(W.strengths(inst.n, m, np.random.default_rng(4), np.complex64))

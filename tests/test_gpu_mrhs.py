@@ -23,7 +23,7 @@ def strengths(n, m, seed):
 
 
 @pytest.mark.parametrize("layout", ["csr", "tiles"])
-@pytest.mark.parametrize("m", [12, 16, 20, 64, 71])
+@pytest.mark.parametrize("m", [6, 12, 16, 20, 33, 64, 71])
 def test_single_plan_many_rhs(layout, m):
     inst = W.sphere(30000, 32, 2 * math.pi * 10, seed=61)
     q = strengths(inst.n, m, 7)
