@@ -169,7 +169,8 @@ p2p_status p2p_batch_create(const p2p_plan* plans, int32_t count, int32_t nrhs, 
 p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y, void* stream);
 
 /* Autotuner: times each launch shape of the product kernel (right-hand sides per
- * work item: 32 or 64; wavefronts per workgroup: 1, 2 or 4) on the given inputs,
+ * work item: 32 or 64, or only 16 (32) when the batch has at most 16 (32);
+ * wavefronts per workgroup: 1, 2 or 4) on the given inputs,
  * keeps the fastest for the batch, and records it in the text file cache_path
  * (one line per workload key; NULL: no file).  A shape found in the file for the
  * same key is taken without timing.  Synchronises stream.  chosen: NULL or

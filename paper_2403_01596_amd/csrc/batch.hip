@@ -170,7 +170,7 @@ static bool cache_lookup(const char* path, const std::string& key, int* width, i
     if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
     std::istringstream rest(line.substr(tab + 1));
     int w = 0, p = 0;
-    if (rest >> w >> p && (w == 32 || w == 64) && (p == 1 || p == 2 || p == 4)) {
+    if (rest >> w >> p && (w == 16 || w == 32 || w == 64) && (p == 1 || p == 2 || p == 4)) {
       *width = w;
       *wpb = p;
       return true;
@@ -185,12 +185,15 @@ p2p_status batch_tune(p2p_batch_s* b, const void* const* q, void* const* y, cons
   int width = 64, wpb = 4;
   if (!cache_lookup(path, key, &width, &wpb)) {
     const BatchIO io = make_io(b, q, y, b->m);
-    const int widths[2] = {64, 32}, wpbs[3] = {4, 2, 1};
+    // item widths worth timing: up to 16 (32) right-hand sides fill only 16-column
+    // (32-column) items, which is also what every call of that size uses
+    const int widths[2] = {b->m <= 16 ? 16 : (b->m <= 32 ? 32 : 64), 32}, wpbs[3] = {4, 2, 1};
+    const int nwidths = b->m <= 32 ? 1 : 2;
     float best = 1e30f;
     hipEvent_t e0, e1;
     P2P_HIP(hipEventCreate(&e0));
     P2P_HIP(hipEventCreate(&e1));
-    for (int wi = 0; wi < 2; ++wi)
+    for (int wi = 0; wi < nwidths; ++wi)
       for (int pi = 0; pi < 3; ++pi) {
         p2p_status rc = run(b, io, widths[wi], wpbs[pi], s);  // warm-up
         if (rc != P2P_OK) return rc;
