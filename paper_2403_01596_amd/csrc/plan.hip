@@ -598,9 +598,12 @@ __device__ __forceinline__ int32_t run_starts(const K* __restrict__ key, int64_t
   return c;
 }
 
+// Also marks every cell of the dense cell table empty (table may be null), ahead of
+// k_runs_write, which enters the boxes.
 template <typename K>
 __global__ void __launch_bounds__(kBlock) k_runs_count(const K* __restrict__ key, int64_t n,
-                                                    int32_t* __restrict__ part) {
+                                                    int32_t* __restrict__ part, int32_t* __restrict__ table,
+                                                    int64_t cells) {
   __shared__ int32_t lds[kBlock / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t mask;
@@ -608,6 +611,8 @@ __global__ void __launch_bounds__(kBlock) k_runs_count(const K* __restrict__ key
   int32_t tot;
   block_exclusive_scan<int32_t>(c, lds, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < cells; i += (int64_t)gridDim.x * kBlock)
+    table[i] = -1;
 }
 
 // part: the tile counts, scanned; status->nbox: the number of boxes.
@@ -1178,6 +1183,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
 
   // dense cell table when the occupied id range is small enough
   CellGrid grid{nullptr, 0, 0, 0, 0, 0};
+  int64_t table_cells = 0;
   {
     const int32_t lo[3] = {(int32_t)(kIdMask - hs.st[ST_LO_X]), (int32_t)(kIdMask - hs.st[ST_LO_Y]),
                            (int32_t)(kIdMask - hs.st[ST_LO_Z])};
@@ -1188,9 +1194,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
       tbl.p = dmem_alloc(sizeof(int32_t) * (size_t)cells);  // no room: fall back to binary search
       if (tbl.p) {
         grid = CellGrid{(int32_t*)tbl.p, lo[0], lo[1], lo[2], ext[0], ext[1]};
-        hipLaunchKernelGGL(k_init, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for((int64_t)cells))),
-                           dim3(kBlock), 0, s, nullptr, (int64_t)0, nullptr, nullptr, (int64_t)0, grid.table,
-                           (int64_t)cells);
+        table_cells = (int64_t)cells;  // marked empty by the box-table pass
       }
     }
   }
@@ -1221,9 +1225,11 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   {
     const unsigned gt = grid_for(n, kScanTile);
     if (sk.k32)
-      hipLaunchKernelGGL(k_runs_count<uint32_t>, dim3(gt), dim3(kBlock), 0, s, sk.k32, n, part32);
+      hipLaunchKernelGGL(k_runs_count<uint32_t>, dim3(gt), dim3(kBlock), 0, s, sk.k32, n, part32, grid.table,
+                         table_cells);
     else
-      hipLaunchKernelGGL(k_runs_count<uint64_t>, dim3(gt), dim3(kBlock), 0, s, sk.k64, n, part32);
+      hipLaunchKernelGGL(k_runs_count<uint64_t>, dim3(gt), dim3(kBlock), 0, s, sk.k64, n, part32, grid.table,
+                         table_cells);
     const ScanIO<int32_t> io{{nullptr, nullptr}, {nullptr, nullptr}, {part32, nullptr}, {&status->nbox, nullptr}};
     hipLaunchKernelGGL(k_scan_partials<int32_t>, dim3(1, 1), dim3(kBlock), 0, s, io, (int64_t)gt);
     if (sk.k32)
