@@ -6,7 +6,8 @@ FP64 oracle.
 - the multi-right-hand-side batch (1M sphere points plus 16 uneven instances,
   64 columns each) in one tuned launch: sampled rows of every instance;
 - the 500k-point cube's reverse pass (dq and dx), FP32 and FP64, against the
-  oracle's full reverse pass;
+  oracle's full reverse pass, and its FP64 dx against central differences (step
+  1e-3, and a Richardson step) of the loss sum |y|^2 computed on the GPU;
 - 2^25 points in the unit cube on a 100^3 grid (a million boxes, a replicated
   list of about 900M entries, close to the 2^31 limit of the 32-bit list
   offsets), both layouts, FP32: tables against the oracle's, sampled rows.
@@ -117,3 +118,41 @@ def test_cube_33m_both_layouts():
         assert err <= TOL[torch.complex64]
         P.close()
         del y
+
+
+def test_cube_500k_dx_finite_differences():
+    inst = W.grad_cube_500k()
+    q = dev(inst.q.astype(np.complex128))
+    ids = dev(inst.ids, torch.int32)
+
+    def loss(x):
+        P = p2p.Plan(dev(x, torch.float64), ids, inst.k, dtype=torch.complex128, layout="csr")
+        val = float((P.apply(q).abs() ** 2).sum().item())
+        P.close()
+        return val
+
+    P = gpu_plan(inst.xyz, inst.ids, inst.k, dtype=torch.complex128, layout="csr")
+    _, dx = P.backward(q, 2 * P.apply(q), want_dq=False)
+    dx = dx.cpu().numpy()
+    P.close()
+    rng = np.random.default_rng(5)
+    errs_plain, errs_rich = [], []
+    for i in rng.choice(inst.n, 6, replace=False):
+        scale = np.abs(dx[i]).max()
+        for a in range(3):
+            d = []
+            for h in (1e-3, 5e-4):
+                xp, xm = inst.xyz.copy(), inst.xyz.copy()
+                xp[i, a] += h
+                xm[i, a] -= h
+                d.append((loss(xp) - loss(xm)) / (2 * h))
+            errs_plain.append(abs(d[0] - dx[i, a]) / scale)
+            errs_rich.append(abs((4 * d[1] - d[0]) / 3 - dx[i, a]) / scale)
+    print("  500k cube, finite differences: median %.2e (h = 1e-3), median %.2e max %.2e (Richardson)" % (
+        np.median(errs_plain), np.median(errs_rich), max(errs_rich)), flush=True)
+    # Truncation: the step-1e-3 difference errs by ~ (h / r)^2 for a point whose nearest
+    # neighbour is r away, about (1e-3 / 0.007)^2 = 2e-2 at this density; Richardson leaves
+    # ~ (h / r)^4, about 4e-4, larger for the few points with a much closer neighbour.
+    assert np.median(errs_plain) < 2e-2
+    assert np.median(errs_rich) < np.median(errs_plain) / 4
+    assert max(errs_rich) < 4e-3
