@@ -230,8 +230,9 @@ class Plan:
 class Batch:
     """Several complex64 plans served together for nrhs right-hand sides on the matrix cores.
 
-    One gather and one product launch per apply, no allocation inside the library
-    call and no synchronisation, so apply_into can be captured in a graph.  The
+    One product launch per apply that reads the strengths in each plan's point
+    order, no allocation inside the library call and no synchronisation, so
+    apply_into can be captured in a graph.  The
     plans must outlive the batch and must have been created with max_rhs >= nrhs.
     """
 
