@@ -67,6 +67,15 @@ struct F32 {
   }
 };
 
+// a * b + c written as one three-operand v_fma_f64.  Given a loop-invariant c,
+// the compiler otherwise picks the two-operand v_fmac_f64, whose addend is also its
+// destination, and copies c into a fresh register pair before every use.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // sin(2 pi x) and cos(2 pi x) for |x| <= 1/4 from their Taylor series in x:
 // coefficients (2 pi)^n / n! with alternating signs, each correctly rounded to
 // double.  The first omitted terms are below 1.3e-18 (sin, x^23) and 1.9e-17 (cos,
@@ -116,23 +125,23 @@ struct F64 {
       // Estrin's scheme (pairs of terms in x2, then x4 and x8): two multiplications
       // more than Horner's rule, and much shorter dependency chains
       const double x4 = x2 * x2, x8 = x4 * x4;
-      const double s01 = __builtin_fma(kSinTurn[1], x2, kSinTurn[0]);
-      const double s23 = __builtin_fma(kSinTurn[3], x2, kSinTurn[2]);
-      const double s45 = __builtin_fma(kSinTurn[5], x2, kSinTurn[4]);
-      const double s67 = __builtin_fma(kSinTurn[7], x2, kSinTurn[6]);
-      const double s89 = __builtin_fma(kSinTurn[9], x2, kSinTurn[8]);
+      const double s01 = fma3(kSinTurn[1], x2, kSinTurn[0]);
+      const double s23 = fma3(kSinTurn[3], x2, kSinTurn[2]);
+      const double s45 = fma3(kSinTurn[5], x2, kSinTurn[4]);
+      const double s67 = fma3(kSinTurn[7], x2, kSinTurn[6]);
+      const double s89 = fma3(kSinTurn[9], x2, kSinTurn[8]);
       const double s0_3 = __builtin_fma(s23, x4, s01);
       const double s4_7 = __builtin_fma(s67, x4, s45);
-      const double s8_10 = __builtin_fma(kSinTurn[10], x4, s89);
+      const double s8_10 = fma3(kSinTurn[10], x4, s89);
       const double ps = __builtin_fma(__builtin_fma(s8_10, x8, s4_7), x8, s0_3);
-      const double c01 = __builtin_fma(kCosTurn[1], x2, kCosTurn[0]);
-      const double c23 = __builtin_fma(kCosTurn[3], x2, kCosTurn[2]);
-      const double c45 = __builtin_fma(kCosTurn[5], x2, kCosTurn[4]);
-      const double c67 = __builtin_fma(kCosTurn[7], x2, kCosTurn[6]);
-      const double c89 = __builtin_fma(kCosTurn[9], x2, kCosTurn[8]);
+      const double c01 = fma3(kCosTurn[1], x2, kCosTurn[0]);
+      const double c23 = fma3(kCosTurn[3], x2, kCosTurn[2]);
+      const double c45 = fma3(kCosTurn[5], x2, kCosTurn[4]);
+      const double c67 = fma3(kCosTurn[7], x2, kCosTurn[6]);
+      const double c89 = fma3(kCosTurn[9], x2, kCosTurn[8]);
       const double c0_3 = __builtin_fma(c23, x4, c01);
       const double c4_7 = __builtin_fma(c67, x4, c45);
-      const double c8_10 = __builtin_fma(kCosTurn[10], x4, c89);
+      const double c8_10 = fma3(kCosTurn[10], x4, c89);
       const double pc = __builtin_fma(__builtin_fma(c8_10, x8, c4_7), x8, c0_3);
       const double hh = 0.5 * h;
       const double sg = __builtin_fma(-4.0, hh - __builtin_floor(hh), 1.0);  // (-1)^h
