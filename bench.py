@@ -273,7 +273,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--sweep-only", action="store_true",
-                    help="only build the FP32 plan and run the apply --apply-reps times (for counter runs)")
+                    help="only build the plan and run the apply --apply-reps times (for counter runs)")
+    ap.add_argument("--sweep-precision", choices=["f32", "f64"], default="f32",
+                    help="precision of the plan that --sweep-only runs")
+    ap.add_argument("--backward-only", action="store_true",
+                    help="only run the reverse pass on its 500k-point cube, FP32 then FP64, "
+                         "--apply-reps times each (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the operator is built and measured on a single MI355X "
@@ -301,6 +306,20 @@ def main():
         print(json.dumps(measure_mrhs(p2p, W, torch, args.apply_reps, not args.no_cpu)))
         return 0
 
+    if args.backward_only:
+        g = W.grad_cube_500k()
+        gx = torch.from_numpy(g.xyz).to(dev)
+        gi = torch.from_numpy(g.ids).to(dev)
+        for dt in (torch.complex64, torch.complex128):
+            q = torch.from_numpy(g.q[:, 0].copy()).to(dev).to(dt)
+            plan = p2p.Plan(gx, gi, g.k, dtype=dt, layout="csr")
+            for _ in range(args.apply_reps):
+                plan.backward(q, q)
+            torch.cuda.synchronize()
+            log("backward-only: %s, %d passes, %d pairs each" % (dt, args.apply_reps, plan.info()["n_pairs"]))
+            plan.close()
+        return 0
+
     inst = W.sphere_2m()
     log("workload %s: n=%d h=%.6g D=%.2f k=%.4f" % (inst.name, inst.n, inst.h, inst.d_mean, inst.k))
     xyz = torch.from_numpy(inst.xyz).to(dev)
@@ -310,9 +329,10 @@ def main():
 
     if args.sweep_only:
         ids = p2p.box_ids(xyz, origin, inst.h)
-        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
+        f64 = args.sweep_precision == "f64"
+        plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex128 if f64 else torch.complex64, layout=args.layout)
         for _ in range(args.apply_reps):
-            plan.apply(q32)
+            plan.apply(q64 if f64 else q32)
         torch.cuda.synchronize()
         log("sweep-only: %d applies, %d pairs each" % (args.apply_reps, plan.info()["n_pairs"]))
         plan.close()

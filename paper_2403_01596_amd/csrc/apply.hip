@@ -15,14 +15,14 @@ namespace p2p {
 
 // y[i, col + c] = scale * sum_j G(r_ij) q[j, col + c] for the M columns c < M of
 // one launch: the kernel value is evaluated once per pair and serves all M.
-// Chunks per group: the precision's count up to 4 columns, half of it for 8
-// (measured on the 2M sphere: fewer chunks leave the 2M per-target sums of a
-// group to too few pairs, more cost occupancy).
+// Chunks per group: the precision's one-column count for one column, its count up
+// to 4 columns, half of it for 8 (measured on the 2M sphere: fewer chunks leave
+// the 2M per-target sums of a group to too few pairs, more cost occupancy).
 template <class Tr, int M = 1>
 struct FwdOp {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
-  static constexpr int K = M <= 4 ? Tr::K : Tr::K / 2, NP = 2 * M, NT = 0, NA = 2 * M;
+  static constexpr int K = M == 1 ? Tr::K1 : (M <= 4 ? Tr::K : Tr::K / 2), NP = 2 * M, NT = 0, NA = 2 * M;
   const cplx* __restrict__ qs;
   int m, col;
   const int32_t* __restrict__ perm;

@@ -13,13 +13,13 @@ namespace p2p {
 
 // M columns per launch: the kernel value, G' and the geometry are formed once per
 // pair and serve every column; dx sums over the columns in one accumulator set.
-// Chunks per group: the precision's count up to 2 columns, half of it for 4
-// (measured on the 500k cube).
+// Chunks per group: the precision's one-column count for one column, its count up
+// to 2 columns, half of it for 4 (measured on the 500k cube).
 template <class Tr, bool DQ, bool DX, int M = 1>
 struct BwdOp {
   using real = typename Tr::real;
   using cplx = typename Tr::cplx;
-  static constexpr int K = M <= 2 ? Tr::K : Tr::K / 2;
+  static constexpr int K = M == 1 ? Tr::K1 : (M <= 2 ? Tr::K : Tr::K / 2);
   static constexpr int NP = 4 * M, NT = DX ? 4 * M : 0, NA = (DQ ? 2 * M : 0) + (DX ? 3 : 0);
   static constexpr int OX = DQ ? 2 * M : 0;  // first dx accumulator
   const cplx* __restrict__ qs;

@@ -285,6 +285,22 @@ __device__ __forceinline__ double wave_sum63(double v) {
   return v;
 }
 
+// The same for doubles: both 32-bit halves take the same lane exchange.
+__device__ __forceinline__ double wave_sum_pair(double a, double b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  const double x = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[0] << 32) | (unsigned)lo[0]);
+  const double y = __builtin_bit_cast(double, ((uint64_t)(unsigned)hi[1] << 32) | (unsigned)lo[1]);
+  double v = x + y;
+  v += dpp_f64<0xb1>(v);
+  v += dpp_f64<0x4e>(v);
+  v += dpp_f64<0x114>(v);
+  v += dpp_f64<0x118>(v);
+  v += dpp_f64<0x142>(v);
+  return v;
+}
+
 // Morton key of box ids: bit 3b <- bit b of x, 3b+1 <- y, 3b+2 <- z.
 __host__ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   uint64_t x = v & 0x1fffffu;

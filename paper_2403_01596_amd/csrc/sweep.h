@@ -38,7 +38,7 @@ struct F32 {
   using coord = int32_t;  // fixed point, units of 2^qexp, low 32 bits
   using real = float;
   using cplx = float2;
-  static constexpr int K = 8;
+  static constexpr int K = 8, K1 = 8;  // chunks of 64 sources per group (K1: one column)
   struct Geo {
     float dx, dy, dz, rinv, c, s;
   };
@@ -93,7 +93,7 @@ struct F64 {
   using coord = double;
   using real = double;
   using cplx = double2;
-  static constexpr int K = 4;
+  static constexpr int K = 4, K1 = 8;  // chunks of 64 sources per group (K1: one column)
   struct Geo {
     double dx, dy, dz, rinv, c, s;
   };
@@ -287,26 +287,17 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
           op.template pair<HELM>(g, P[c], tp, acc);
         }
       }
-    if constexpr (std::is_same<real, float>::value) {
-      // accumulators in pairs: the even one's sum lands in lane 31, the odd one's
-      // (and a last unpaired one's) in lane 63
+    // accumulators in pairs: the even one's sum lands in lane 31, the odd one's
+    // (and a last unpaired one's) in lane 63
 #pragma unroll
-      for (int a = 0; a + 1 < NA; a += 2) acc[a] = acc[a + 1] = wave_sum_pair(acc[a], acc[a + 1]);
-      if (NA % 2) acc[NA - 1] = wave_sum63(acc[NA - 1]);
-      if (lane == 31 || lane == kWave - 1) {
+    for (int a = 0; a + 1 < NA; a += 2) acc[a] = acc[a + 1] = wave_sum_pair(acc[a], acc[a + 1]);
+    if (NA % 2) acc[NA - 1] = wave_sum63(acc[NA - 1]);
+    if (lane == 31 || lane == kWave - 1) {
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const bool in63 = (a & 1) || a == NA - 1;
-          if ((lane == kWave - 1) == in63)
-            L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < NA; ++a) acc[a] = wave_sum63(acc[a]);
-      if (lane == kWave - 1) {
-#pragma unroll
-        for (int a = 0; a < NA; ++a) L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
+      for (int a = 0; a < NA; ++a) {
+        const bool in63 = (a & 1) || a == NA - 1;
+        if ((lane == kWave - 1) == in63)
+          L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
       }
     }
   }
