@@ -85,6 +85,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def spin_up(fn, torch):
+    """Untimed calls of fn for SPIN_UP_S seconds: after an idle spell (plan builds,
+    host work) the clock takes tens of milliseconds to climb back to its steady
+    value, and a short timed loop would otherwise run on that ramp."""
+    end = time.perf_counter() + SPIN_UP_S
+    while time.perf_counter() < end:
+        fn()
+        torch.cuda.synchronize()
+
+
 def kernel_source_digest(sources=None) -> str:
     h = hashlib.sha256()
     for f in sources or KERNEL_SOURCES:
@@ -197,7 +207,7 @@ def measure_backward(p2p, W, torch, reps):
         plan = p2p.Plan(xyz, ids, inst.k, dtype=dt, layout="csr")
         n_pairs = plan.info()["n_pairs"]
         plan.backward(q, g)
-        torch.cuda.synchronize()
+        spin_up(lambda: plan.backward(q, g), torch)
         plan.timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -237,7 +247,7 @@ def measure_layouts(p2p, W, torch, reps):
             plan_ms = (time.perf_counter() - t0) * 1e3
             n_pairs = plan.info()["n_pairs"]
             plan.apply(q)
-            torch.cuda.synchronize()
+            spin_up(lambda: plan.apply(q), torch)
             plan.timing(True)
             for _ in range(reps):
                 plan.apply(q)
@@ -313,10 +323,15 @@ def main():
         for dt in (torch.complex64, torch.complex128):
             q = torch.from_numpy(g.q[:, 0].copy()).to(dev).to(dt)
             plan = p2p.Plan(gx, gi, g.k, dtype=dt, layout="csr")
+            spin_up(lambda: plan.backward(q, q), torch)
+            plan.timing(True)
             for _ in range(args.apply_reps):
                 plan.backward(q, q)
             torch.cuda.synchronize()
-            log("backward-only: %s, %d passes, %d pairs each" % (dt, args.apply_reps, plan.info()["n_pairs"]))
+            kern_ms, calls = plan.timing_read()
+            plan.timing(False)
+            log("backward-only: %s, %d timed passes, %d pairs each, sweep kernel %.4f ms (HIP events)" % (
+                dt, args.apply_reps, plan.info()["n_pairs"], kern_ms / calls))
             plan.close()
         return 0
 
@@ -393,6 +408,7 @@ def main():
     n_pairs = info["n_pairs"]
 
     def time_apply(plan, q, reps):
+        spin_up(lambda: plan.apply(q), torch)
         plan.timing(True)
         plan.apply(q)
         torch.cuda.synchronize()
