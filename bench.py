@@ -85,6 +85,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def single_core_oracle(W, oracle):
+    """The oracle on one thread: the 8192-point cube (every row) and a bounded
+    sample of rows of the 500k-point cube."""
+    out = {}
+    c1 = W.plain_f64_cube()
+    orc = oracle.Plan(c1.ids)
+    pairs = orc.stats(c1.xyz)["n_pairs"]
+    t0 = time.perf_counter()
+    orc.apply(c1.xyz, c1.k, c1.q, threads=1)
+    out["cube8192_g8"] = {"gpairs_s": round(pairs / (time.perf_counter() - t0) / 1e9, 5), "rows": c1.n,
+                          "pairs": pairs}
+    c5 = W.grad_cube_500k()
+    orc = oracle.Plan(c5.ids)
+    rows = np.arange(0, c5.n, 50)
+    tb = orc.tables()
+    sizes = np.diff(tb["box_start"]).astype(np.int64)
+    nsrc = np.array([sizes[tb["nbr_idx"][tb["nbr_start"][T]:tb["nbr_start"][T + 1]]].sum()
+                     for T in range(sizes.size)])
+    pos = np.empty(c5.n, np.int64)
+    pos[tb["perm"]] = np.arange(c5.n)
+    box = np.searchsorted(tb["box_start"], pos[rows], side="right") - 1
+    pairs = int(nsrc[box].sum() - rows.size)  # distinct points: each row skips its self pair
+    t0 = time.perf_counter()
+    orc.apply_rows(c5.xyz, c5.k, c5.q, rows, threads=1)
+    out["cube500k_g25_every_50th_row"] = {"gpairs_s": round(pairs / (time.perf_counter() - t0) / 1e9, 5),
+                                          "rows": int(rows.size), "pairs": pairs}
+    return out
+
+
 def spin_up(fn, torch):
     """Untimed calls of fn for SPIN_UP_S seconds: after an idle spell (plan builds,
     host work) the clock takes tens of milliseconds to climb back to its steady
@@ -176,14 +215,23 @@ def measure_mrhs(p2p, W, torch, reps, with_oracle):
                         "kernel": "k_mrhs (FP32 MFMA 16x16x4, CSR)"}}
     if with_oracle:
         import oracle
-        num = den = 0.0
-        for inst, y in zip(insts, ys):
-            rows = np.random.default_rng(1).choice(inst.n, min(inst.n, 400), replace=False)
+        from scipy.spatial import cKDTree
+        per = []
+        for j, (inst, y) in enumerate(zip(insts, ys)):
+            got = y.cpu().numpy()
+            if j == 0:  # the 1M instance: every row
+                ref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, inst.q)
+                out["rel_err_main_all_rows"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                continue
+            # the small instances: 400 random rows plus the rows of the 20 closest pairs
+            dist, nb = cKDTree(inst.xyz).query(inst.xyz, k=2)
+            close = np.argsort(dist[:, 1])[:20]
+            rows = np.unique(np.concatenate([np.random.default_rng(1).choice(inst.n, min(inst.n, 400), replace=False),
+                                             close, nb[close, 1]]))
             ref = oracle.Plan(inst.ids).apply_rows(inst.xyz, inst.k, inst.q, rows)
-            got = y.cpu().numpy()[rows]
-            num += float(np.sum(np.abs(got - ref) ** 2))
-            den += float(np.sum(np.abs(ref) ** 2))
-        out["rel_err_sampled_rows"] = math.sqrt(num / den)
+            per.append(float(np.linalg.norm(got[rows] - ref) / np.linalg.norm(ref)))
+        out["rel_err_small_instances_max"] = max(per)
+        out["rel_err_small_instances_sample"] = "400 random rows + the rows of the 20 closest pairs, per instance"
     log("multi-RHS: graph %.3f ms, kernel %.3f ms, %.3g pair-RHS/s, %.1f%% of FP32 MFMA peak" % (
         graph_ms, kern_ms, out["pair_rhs_per_s"], 100 * out["roofline"]["frac"]))
     batch.close()
@@ -192,21 +240,32 @@ def measure_mrhs(p2p, W, torch, reps, with_oracle):
     return out
 
 
-def measure_backward(p2p, W, torch, reps):
+def measure_backward(p2p, W, torch, reps, with_oracle):
     """Reverse pass (dq and dx in one sweep) on 500k uniform points in a 25^3 grid,
     k = 2 pi * 16, FP32 and FP64, CSR layout; sweep kernel time from the library's
-    events."""
+    events; relative L2 errors of dq and dx over every row against the oracle's
+    reverse pass."""
     inst = W.grad_cube_500k()
     xyz = torch.from_numpy(inst.xyz).cuda()
     ids = torch.from_numpy(inst.ids).cuda()
     g64 = W.strengths(inst.n, 1, np.random.default_rng(5), np.complex128)
     out = {"workload": "cube500k_g25 (500k uniform points, 25^3 boxes, k = 2 pi 16), dq and dx"}
+    orc = None
+    if with_oracle:
+        import oracle
+        orc = oracle.Plan(inst.ids)
     for dt, name in ((torch.complex64, "f32"), (torch.complex128, "f64")):
-        q = torch.from_numpy(inst.q.astype(np.complex64 if name == "f32" else np.complex128)).cuda()
-        g = torch.from_numpy(g64.astype(np.complex64 if name == "f32" else np.complex128)).cuda()
+        npd = np.complex64 if name == "f32" else np.complex128
+        q = torch.from_numpy(inst.q.astype(npd)).cuda()
+        g = torch.from_numpy(g64.astype(npd)).cuda()
         plan = p2p.Plan(xyz, ids, inst.k, dtype=dt, layout="csr")
         n_pairs = plan.info()["n_pairs"]
-        plan.backward(q, g)
+        dq, dx = plan.backward(q, g)
+        errs = None
+        if orc is not None:
+            dq_ref, dx_ref = orc.backward(inst.xyz, inst.k, inst.q.astype(npd), g64.astype(npd))
+            errs = {"dq": float(np.linalg.norm(dq.cpu().numpy() - dq_ref) / np.linalg.norm(dq_ref)),
+                    "dx": float(np.linalg.norm(dx.cpu().numpy() - dx_ref) / np.linalg.norm(dx_ref))}
         spin_up(lambda: plan.backward(q, g), torch)
         plan.timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -220,7 +279,7 @@ def measure_backward(p2p, W, torch, reps):
         kern_ms /= calls
         call_ms = e0.elapsed_time(e1) / reps
         out[name] = {"n_pairs": n_pairs, "call_ms": round(call_ms, 4), "kernel_ms": round(kern_ms, 4),
-                     "gpairs_s": round(n_pairs / kern_ms / 1e6, 2)}
+                     "gpairs_s": round(n_pairs / kern_ms / 1e6, 2), "rel_err": errs}
         plan.close()
     out["roofline_f32"] = {"bound": "alu", "achieved": out["f32"]["gpairs_s"], "peak": round(PEAK_BWD_GPAIRS, 1),
                            "unit": "Gpair/s", "frac": round(out["f32"]["gpairs_s"] / PEAK_BWD_GPAIRS, 4),
@@ -230,23 +289,32 @@ def measure_backward(p2p, W, torch, reps):
     return out
 
 
-def measure_layouts(p2p, W, torch, reps):
+def measure_layouts(p2p, W, torch, reps, with_oracle):
     """The two source layouts on 4M points of the (1, 0.5, 0.25) ellipsoid at 16, 32
-    and 64 points per box (k = pi / (2h)), FP32: plan build and sweep kernel."""
+    and 64 points per box (k = pi / (2h)), FP32: plan build and sweep kernel, and the
+    relative L2 error of every output row against the oracle."""
     out = {"workload": "ellipsoid4M at D = 16, 32, 64, k = pi / (2h), FP32"}
     for d in (16, 32, 64):
         inst = W.ellipsoid_4m(d)
         xyz = torch.from_numpy(inst.xyz).cuda()
         ids = torch.from_numpy(inst.ids).cuda()
         q = torch.from_numpy(inst.q[:, 0].copy()).cuda()
+        ref = None
+        if with_oracle:
+            import oracle
+            ref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, inst.q)[:, 0]
         row = {}
         for layout in ("tiles", "csr"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=layout)
             plan_ms = (time.perf_counter() - t0) * 1e3
-            n_pairs = plan.info()["n_pairs"]
-            plan.apply(q)
+            info = plan.info()
+            n_pairs = info["n_pairs"]
+            y = plan.apply(q)
+            err = None
+            if ref is not None:
+                err = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
             spin_up(lambda: plan.apply(q), torch)
             plan.timing(True)
             for _ in range(reps):
@@ -256,14 +324,14 @@ def measure_layouts(p2p, W, torch, reps):
             plan.timing(False)
             kern_ms /= calls
             row[layout] = {"plan_ms": round(plan_ms, 3), "sweep_ms": round(kern_ms, 4),
-                           "gpairs_s": round(n_pairs / kern_ms / 1e6, 2),
-                           "device_bytes": plan.info()["device_bytes"]}
+                           "gpairs_s": round(n_pairs / kern_ms / 1e6, 2), "rel_err": err,
+                           "close_pairs": info["n_close_pairs"], "device_bytes": info["device_bytes"]}
             plan.close()
         row["n_pairs"] = n_pairs
         out["D%d" % d] = row
-        log("ellipsoid D=%d: %d pairs; tiles %.1f Gpair/s (plan %.2f ms), csr %.1f Gpair/s (plan %.2f ms)" % (
-            d, n_pairs, row["tiles"]["gpairs_s"], row["tiles"]["plan_ms"], row["csr"]["gpairs_s"],
-            row["csr"]["plan_ms"]))
+        log("ellipsoid D=%d: %d pairs; tiles %.1f Gpair/s (plan %.2f ms, err %s), csr %.1f Gpair/s (plan %.2f ms, "
+            "err %s)" % (d, n_pairs, row["tiles"]["gpairs_s"], row["tiles"]["plan_ms"], row["tiles"]["rel_err"],
+                         row["csr"]["gpairs_s"], row["csr"]["plan_ms"], row["csr"]["rel_err"]))
     return out
 
 
@@ -369,12 +437,22 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # every timed step bracketed by HIP events on the stream the step runs on (the
+    # plan build's host waits show up as gaps between its kernels, so the events
+    # measure the step as the GPU sees it, waits included); the headline is the
+    # median step
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in evs:
+        e0.record()
         y32 = step()
+        e1.record()
     torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t0) / args.steps
-    log("step %.3f ms" % (step_s * 1e3))
+    wall_s = (time.perf_counter() - t0) / args.steps
+    step_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    step_s = float(np.median(step_ms)) * 1e-3
+    log("step: median %.3f ms, mean %.3f ms (events), %.3f ms (host clock)" % (
+        step_s * 1e3, step_ms.mean(), wall_s * 1e3))
 
     # ---- where the step's time goes: each phase bracketed by synchronisations
     phases = {"plan_create": 0.0, "apply": 0.0, "release": 0.0}
@@ -406,6 +484,12 @@ def main():
     plan_s = time.perf_counter() - t0
     info = plan32.info()
     n_pairs = info["n_pairs"]
+    # the plan build against the HBM roofline: the bytes it must move at least
+    # (positions read once; permutation, FP64 and fixed-point sorted coordinates,
+    # box tables and neighbour lists written once), over the measured build of the
+    # timed step (ids computed inside the build, so no id array is read)
+    plan_bytes = (inst.n * (24 + 4 + 24 + 12) + info["n_boxes"] * (8 + 4 * 4) + info["n_nbr"] * 4
+                  + info["tile_entries"] * (4 + 12))
 
     def time_apply(plan, q, reps):
         spin_up(lambda: plan.apply(q), torch)
@@ -465,9 +549,11 @@ def main():
         yref = orc.apply_rows(inst.xyz, inst.k, inst.q, rows, threads=threads)
         cpu_s = time.perf_counter() - t0
         cpu = {"value": round(pairs_sample / cpu_s / 1e9, 5), "unit": "Gpair/s", "cores": threads,
-               "kind": "oracle", "seconds": round(cpu_s, 2),
+               "kind": "oracle", "seconds": round(cpu_s, 2), "cpu_model": cpu_model(),
+               "host_threads": os.cpu_count(),
                "sample": "every target row of the same 2M-point input (%d rows, %d pairs), "
-                         "FP64, OpenMP over rows" % (rows.size, pairs_sample)}
+                         "FP64, OpenMP over rows" % (rows.size, pairs_sample),
+               "single_core": single_core_oracle(W, oracle)}
         y32h = y32.cpu().numpy()[rows]
         y64h = y64.cpu().numpy()[rows]
         ref = yref[:, 0]
@@ -476,14 +562,19 @@ def main():
         log("oracle %.1f s on %d threads; rel L2 f32 %.3e f64 %.3e" % (cpu_s, threads, errs["f32"], errs["f64"]))
     plan32.close()
     mrhs = None if args.no_mrhs else measure_mrhs(p2p, W, torch, max(3, args.apply_reps // 4), not args.no_cpu)
-    backward = None if args.no_extra else measure_backward(p2p, W, torch, max(3, args.apply_reps // 4))
-    layouts = None if args.no_extra else measure_layouts(p2p, W, torch, max(3, args.apply_reps // 4))
+    backward = None if args.no_extra else measure_backward(p2p, W, torch, max(3, args.apply_reps // 4),
+                                                           not args.no_cpu)
+    layouts = None if args.no_extra else measure_layouts(p2p, W, torch, max(3, args.apply_reps // 4),
+                                                         not args.no_cpu)
 
     value = n_pairs / step_s / 1e9
     line = {
         "metric": "near-field interactions/s (G-pairs/s) at stated rel-err; % of VALU/HBM roofline",
         "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "step_timing": {"statistic": "median of %d per-step HIP event intervals" % args.steps,
+                        "mean_ms": round(float(step_ms.mean()), 4), "min_ms": round(float(step_ms.min()), 4),
+                        "max_ms": round(float(step_ms.max()), 4), "host_clock_mean_ms": round(wall_s * 1e3, 4)},
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": inst.name, "n_points": inst.n, "k": inst.k, "leaf_h": inst.h,
                    "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": args.layout,
@@ -504,6 +595,12 @@ def main():
                                                     % F64_SLOTS_PER_PAIR}},
         "plan_ms": round(plan_s * 1e3, 3),
         "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "plan_roofline": {"bound": "hbm", "algorithmic_bytes": plan_bytes,
+                          "achieved": round(plan_bytes / (phases["plan_create"] * 1e-3) / 1e9, 1),
+                          "peak": 8000.0, "unit": "GB/s",
+                          "frac": round(plan_bytes / (phases["plan_create"] * 1e-3) / 8e12, 4),
+                          "bytes_per_point": "24 read (positions) + 40 written (permutation, FP64 and fixed-point "
+                                             "coordinates) + 24 per box + 4 per neighbour-list entry"},
         "box_ids_call_ms": round(box_ids_ms, 4),
         "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"]},
         "roofline": roofline,

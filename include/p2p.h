@@ -74,6 +74,10 @@ typedef struct {
   p2p_layout layout;
   int32_t max_rhs;     /* largest nrhs accepted by apply and backward (>= 1)        */
   uint32_t flags;      /* reserved, must be 0                                      */
+  const char* tune_cache; /* NULL, or an autotuner cache file (p2p_batch_tune): a
+                             complex64 plan with max_rhs >= 6 serves many right-hand
+                             sides with the launch shape recorded there for its
+                             workload, if any (read at creation, never timed)      */
 } p2p_opts;
 
 typedef struct {
@@ -89,6 +93,8 @@ typedef struct {
   int32_t quantum_exp;  /* FP32 plans: coordinates are integers in units of 2^e    */
   double d_mean;        /* n_points / n_boxes                                      */
   double max_sep;       /* largest per-axis coordinate difference of a near pair   */
+  int64_t n_close_pairs; /* FP32 plans: ordered near pairs closer than 2^20 quanta,
+                            whose kernel values come from the FP64 coordinates     */
 } p2p_info;
 
 /* Leaf-box ids from positions: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h),
@@ -124,22 +130,34 @@ p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* orig
  * the device the first time they are asked for (synchronously). */
 p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out);
 
-/* Copies the plan's tables to host memory (any pointer may be NULL):
+/* Copies the plan's tables to host memory (any pointer may be NULL): the boxes in
+ * Morton order with their points, and each box's neighbour boxes (paper section
+ * 3.2: targets and neighbour sources of every box, with their offset arrays):
  * box_key u64[B], box_start i32[B+1], perm i32[n] (sorted position -> original
  * index), nbr_start i32[B+1], nbr_idx i32[n_nbr].  Synchronous. */
 p2p_status p2p_plan_export(p2p_plan plan, uint64_t* box_key, int32_t* box_start, int32_t* perm, int32_t* nbr_start,
                            int32_t* nbr_idx);
 
-/* y = A_near q for nrhs right-hand sides.  dtype must equal the plan's precision;
- * 1 <= nrhs <= max_rhs.  y is overwritten.  Asynchronous on stream. */
+/* y = A_near q for nrhs right-hand sides (paper sections 3.2 and 3.3: every target
+ * sums, over the sources of its own and the adjacent boxes, the kernel value times
+ * the source's strength; section 1 names this the P2P operator of the near field).
+ * q and y: [n, nrhs] in the caller's point order.  dtype must equal the plan's
+ * precision; 1 <= nrhs <= max_rhs.  y is overwritten.  FP32 plans: the kernel
+ * value of every near pair closer than 2^20 quanta comes from the FP64
+ * coordinates (p2p_info.n_close_pairs), the others from fixed-point differences.
+ * Asynchronous on stream. */
 p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dtype dtype, void* stream);
 
-/* Reverse pass for a real loss L(y), given grad_y = dL/dRe y + i dL/dIm y:
+/* Reverse pass of p2p_apply (the adjoint of the operator of paper sections 3.2 and
+ * 3.3; the paper itself has no gradients) for a real loss L(y), given
+ * grad_y = dL/dRe y + i dL/dIm y:
  *   grad_q = conj(A conj(grad_y))      (A is complex symmetric),
  *   grad_xyz[i] = sum_j sum_c Re( G'(r_ij) (conj(gy_ic) q_jc + conj(gy_jc) q_ic) ) (x_i - x_j) / r_ij,
  *   G'(r) = exp(i k r) (i k r - 1) / (4 pi r^2),
- * with the ids (and so the pair set) held fixed.  grad_q or grad_xyz may be NULL.
- * grad_xyz is float64 [n,3].  Asynchronous on stream. */
+ * with the ids (and so the pair set) held fixed.  q, grad_y, grad_q: [n, nrhs] in
+ * the caller's point order; grad_xyz: float64 [n,3].  grad_q or grad_xyz may be
+ * NULL (not computed).  The same pairs as p2p_apply (close pairs of FP32 plans
+ * included).  Asynchronous on stream. */
 p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, void* grad_q, double* grad_xyz,
                               int32_t nrhs, p2p_dtype dtype, void* stream);
 
@@ -163,7 +181,10 @@ p2p_status p2p_plan_timing_read(p2p_plan plan, double* ms, int64_t* calls);
  * synchronisation (capturable in a HIP graph, replayable with the same pointers).
  * Plans created with max_rhs >= 6 use the same path from p2p_apply when
  * nrhs >= 6.  A call with nrhs <= 16 (<= 32) uses 16 (32) columns per work item,
- * whatever the autotuner chose. */
+ * whatever the autotuner chose.  Errors: P2P_ERR_STATE for a plan or batch handle
+ * that is not live, P2P_ERR_ARG for null arrays or count/nrhs out of range,
+ * P2P_ERR_DTYPE for a complex128 plan, P2P_ERR_NOMEM when the batch's tables do
+ * not fit. */
 typedef struct p2p_batch_s* p2p_batch;
 p2p_status p2p_batch_create(const p2p_plan* plans, int32_t count, int32_t nrhs, p2p_batch* out);
 p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y, void* stream);
@@ -177,12 +198,22 @@ p2p_status p2p_batch_apply(p2p_batch batch, const void* const* q, void* const* y
  * int32[2] receiving (right-hand sides per item, wavefronts per workgroup). */
 p2p_status p2p_batch_tune(p2p_batch batch, const void* const* q, void* const* y, const char* cache_path,
                           void* stream, int32_t* chosen);
+/* Diagnostics as p2p_plan_timing / p2p_plan_timing_read, around the product kernel. */
 p2p_status p2p_batch_timing(p2p_batch batch, int enable);
 p2p_status p2p_batch_timing_read(p2p_batch batch, double* ms, int64_t* calls);
+/* Frees the batch (not its plans) after its last p2p_batch_apply outside graph
+ * capture has finished.  NULL is a no-op; a handle that is not a live batch gives
+ * P2P_ERR_STATE and is not read. */
 p2p_status p2p_batch_destroy(p2p_batch batch);
 
-/* Frees the plan.  Synchronises the device first, so work already enqueued with
- * the plan finishes before its memory is released.  NULL is a no-op. */
+/* Frees the plan.  Waits first for the work of the plan's last p2p_apply or
+ * p2p_apply_backward call outside graph capture (calls on one plan are ordered,
+ * so this covers every earlier one); graphs that captured the plan's work must
+ * not be replayed after this.  NULL is a no-op; a handle that is not a live plan
+ * (destroyed already, or never created) gives P2P_ERR_STATE and is not read.
+ * Plan creation fails with P2P_ERR_NOMEM when device memory runs out; the
+ * environment variable P2P_TEST_FAIL_ALLOC=n makes the library's n-th device
+ * allocation after the variable is set (or changed) fail that way, for tests. */
 p2p_status p2p_plan_destroy(p2p_plan plan);
 
 const char* p2p_status_str(p2p_status s);

@@ -35,14 +35,15 @@ class P2PError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("layout", ctypes.c_int), ("max_rhs", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("tune_cache", ctypes.c_char_p)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int64), ("n_nbr", ctypes.c_int64),
                 ("n_slots", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_zero_pairs", ctypes.c_int64),
                 ("tile_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("t_max", ctypes.c_int32),
-                ("quantum_exp", ctypes.c_int32), ("d_mean", ctypes.c_double), ("max_sep", ctypes.c_double)]
+                ("quantum_exp", ctypes.c_int32), ("d_mean", ctypes.c_double), ("max_sep", ctypes.c_double),
+                ("n_close_pairs", ctypes.c_int64)]
 
 
 _lib = None
@@ -121,9 +122,11 @@ class Plan:
     """Near-field plan of one point set: boxes, neighbour lists and source lists on the device."""
 
     def __init__(self, xyz: torch.Tensor, ids: torch.Tensor, k: float, dtype=torch.complex64, layout: str = "tiles",
-                 max_rhs: int = 1):
+                 max_rhs: int = 1, tune_cache: Optional[str] = None):
         if dtype not in (torch.complex64, torch.complex128):
             raise TypeError("dtype must be complex64 or complex128")
+        # the positions the plan copies: P2PFunction checks that it is given these
+        self._xyz_src, self._xyz_version = xyz, getattr(xyz, "_version", None)
         xyz = _cuda(xyz, torch.float64, "xyz")
         if ids is not None:
             ids = _cuda(ids, torch.int32, "ids")
@@ -135,7 +138,8 @@ class Plan:
         self.n = xyz.shape[0]
         self.max_rhs = int(max_rhs)
         self.device = xyz.device
-        opts = _Opts(P2P_C64 if dtype == torch.complex64 else P2P_C128, LAYOUTS[layout], self.max_rhs, 0)
+        opts = _Opts(P2P_C64 if dtype == torch.complex64 else P2P_C128, LAYOUTS[layout], self.max_rhs, 0,
+                     tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
         if ids is None:  # leaf grid given by from_grid
             org = (ctypes.c_double * 3)(*self._grid[0])
@@ -148,11 +152,11 @@ class Plan:
 
     @classmethod
     def from_grid(cls, xyz: torch.Tensor, origin, h: float, k: float, dtype=torch.complex64, layout: str = "tiles",
-                  max_rhs: int = 1) -> "Plan":
+                  max_rhs: int = 1, tune_cache: Optional[str] = None) -> "Plan":
         """The plan with leaf-box ids floor((xyz - origin) / h) computed inside the build."""
         self = cls.__new__(cls)
         self._grid = ([float(v) for v in origin], float(h))
-        cls.__init__(self, xyz, None, k, dtype=dtype, layout=layout, max_rhs=max_rhs)
+        cls.__init__(self, xyz, None, k, dtype=dtype, layout=layout, max_rhs=max_rhs, tune_cache=tune_cache)
         return self
 
     @property
@@ -187,6 +191,21 @@ class Plan:
         _check(lib().p2p_plan_export(self.handle, p(out["box_key"]), p(out["box_start"]), p(out["perm"]),
                                      p(out["nbr_start"]), p(out["nbr_idx"])))
         return out
+
+    def check_positions(self, xyz: torch.Tensor):
+        """Raises unless xyz holds the positions the plan was built from.
+
+        The plan keeps its own copy of the positions (sorted, with the quantised
+        form of FP32 plans), so positions that moved after the build, in place or
+        in another tensor, would give y and dx for the old ones.
+        """
+        src = self._xyz_src
+        if src._version != self._xyz_version:
+            raise ValueError("the positions this plan was built from were modified in place since; "
+                             "build a new plan for the new positions")
+        if xyz is not src:
+            if xyz.shape != src.shape or xyz.device != src.device or not torch.equal(xyz.detach(), src.detach()):
+                raise ValueError("xyz differs from the positions this plan was built from; build a new plan")
 
     def timing(self, enable: bool = True):
         """Record HIP events around the sweep kernels of later apply/backward calls."""
@@ -304,12 +323,14 @@ class P2PFunction(torch.autograd.Function):
     """y = A_near(xyz) q, differentiable in q and in the positions.
 
     The plan fixes the near-field pair set (the ids) and holds the positions it was
-    built from; xyz must be that tensor.  Gradients follow the real-loss convention
-    grad = dL/dRe + i dL/dIm.
+    built from; xyz must hold those positions (the tensor the plan was built from,
+    unmodified, or one equal to it), else forward raises.  Gradients follow the
+    real-loss convention grad = dL/dRe + i dL/dIm.
     """
 
     @staticmethod
     def forward(ctx, xyz: torch.Tensor, q: torch.Tensor, plan: Plan):
+        plan.check_positions(xyz)
         ctx.plan = plan
         ctx.save_for_backward(q)
         return plan.apply(q)

@@ -4,6 +4,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 
 #include "mrhs.h"
 
@@ -23,8 +24,39 @@ p2p_status hip_fail(hipError_t e, const char* what) {
   return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? P2P_ERR_NOMEM : P2P_ERR_HIP;
 }
 
+namespace {
+std::mutex g_handles_mu;
+std::unordered_set<const void*>* g_handles = nullptr;  // never freed: handles may outlive static destruction
+}  // namespace
+
+void handle_add(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  if (!g_handles) g_handles = new std::unordered_set<const void*>();
+  g_handles->insert(h);
+}
+
+void handle_remove(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  if (g_handles) g_handles->erase(h);
+}
+
+bool handle_live(const void* h) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  return g_handles && g_handles->count(h) != 0;
+}
+
+void record_use(hipEvent_t ev, hipStream_t s) {
+  if (!ev) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (cs == hipStreamCaptureStatusNone) (void)hipEventRecord(ev, s);
+}
+
 static p2p_status check_plan(p2p_plan_s* P) {
-  if (!P || P->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle");
+  if (!P || !handle_live(P) || P->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle");
   return P2P_OK;
 }
 
@@ -55,17 +87,24 @@ static void drop_events(p2p_plan_s* P) {
   P->timed->clear();
 }
 
+// Waits for the plan's last recorded work (its calls are ordered, so that covers
+// every earlier one), then releases everything.
 static p2p_status free_plan(p2p_plan_s* P) {
   p2p_status rc = P2P_OK;
+  handle_remove(P);
   int cur = P->device;
   (void)hipGetDevice(&cur);
   if (cur != P->device) (void)hipSetDevice(P->device);
-  if (hipDeviceSynchronize() != hipSuccess) rc = fail(P2P_ERR_HIP, "hipDeviceSynchronize failed in destroy");
+  if (P->last_use) {
+    if (hipEventSynchronize(P->last_use) != hipSuccess) rc = fail(P2P_ERR_HIP, "hipEventSynchronize failed in destroy");
+    (void)hipEventDestroy(P->last_use);
+  }
   if (P->self_batch) batch_free(P->self_batch);
   drop_events(P);
   delete P->timed;
   dmem_free(P->arena);
   dmem_free(P->arena2);
+  dmem_free(P->arena3);
   if (cur != P->device) (void)hipSetDevice(cur);
   P->magic = 0;
   delete P;
@@ -116,7 +155,7 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   // neighbour-list entries (at most 27 n) are 32-bit offsets
   if (n > (int64_t)(0x7fffffff / 27)) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
   if (!std::isfinite(k) || k < 0) return fail(P2P_ERR_RANGE, "k must be finite and >= 0");
-  p2p_opts o{P2P_C64, P2P_LAYOUT_TILES, 1, 0u};
+  p2p_opts o{P2P_C64, P2P_LAYOUT_TILES, 1, 0u, nullptr};
   if (opts) o = *opts;
   if (o.precision != P2P_C64 && o.precision != P2P_C128) return fail(P2P_ERR_ARG, "unknown precision");
   if (o.layout != P2P_LAYOUT_TILES && o.layout != P2P_LAYOUT_CSR) return fail(P2P_ERR_ARG, "unknown layout");
@@ -141,9 +180,17 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
     delete P;
     return fail(P2P_ERR_NOMEM, "host allocation failed");
   }
-  p2p_status rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, (hipStream_t)stream);
-  if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin)
+  handle_add(P);
+  p2p_status rc = P2P_OK;
+  if (hipEventCreateWithFlags(&P->last_use, hipEventDisableTiming) != hipSuccess) {
+    P->last_use = nullptr;
+    rc = fail(P2P_ERR_HIP, "hipEventCreateWithFlags failed");
+  }
+  if (rc == P2P_OK) rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, (hipStream_t)stream);
+  if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin) {
     rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
+    if (rc == P2P_OK && o.tune_cache) batch_use_cache(P->self_batch, o.tune_cache);
+  }
   if (rc != P2P_OK) {
     std::string msg = g_last_error;
     free_plan(P);
@@ -202,6 +249,7 @@ p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {
   out->quantum_exp = plan->precision == P2P_C64 ? plan->qexp : 0;
   out->d_mean = plan->B ? (double)plan->n / (double)plan->B : 0.0;
   out->max_sep = plan->max_sep;
+  out->n_close_pairs = plan->n_close;
   return P2P_OK;
 }
 
@@ -235,9 +283,12 @@ p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dt
   if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
   if (plan->self_batch && nrhs >= kMrhsMin) {
     void* yy = y;
-    return batch_apply(plan->self_batch, &q, &yy, nrhs, (hipStream_t)stream, plan->timing, plan->timed);
+    rc = batch_apply(plan->self_batch, &q, &yy, nrhs, (hipStream_t)stream, plan->timing, plan->timed);
+  } else {
+    rc = launch_apply(plan, q, y, nrhs, (hipStream_t)stream);
   }
-  return launch_apply(plan, q, y, nrhs, (hipStream_t)stream);
+  if (rc == P2P_OK) record_use(plan->last_use, (hipStream_t)stream);
+  return rc;
 }
 
 p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, void* grad_q, double* grad_xyz,
@@ -245,7 +296,9 @@ p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, 
   p2p_status rc = check_call(plan, nrhs, dtype);
   if (rc != P2P_OK) return rc;
   if (plan->n > 0 && (!q || !grad_y)) return fail(P2P_ERR_ARG, "q or grad_y is NULL");
-  return launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
+  rc = launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
+  if (rc == P2P_OK) record_use(plan->last_use, (hipStream_t)stream);
+  return rc;
 }
 
 p2p_status p2p_plan_timing(p2p_plan plan, int enable) {

@@ -17,6 +17,7 @@ struct p2p_batch_s {
   void* mem;                   // device: descriptors and both item lists
   p2p::MrhsSetup set64, set32, set16;  // items for 64, 32 and 16 right-hand sides per item
   int width, wpb;              // launch shape
+  hipEvent_t last_use;         // recorded after each apply: destroy waits for it
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
 };
@@ -26,12 +27,17 @@ namespace p2p {
 constexpr uint64_t kBatchMagic = 0x7032705f62617463ull;
 
 static p2p_status check_batch(p2p_batch_s* b) {
-  if (!b || b->magic != kBatchMagic) return fail(P2P_ERR_STATE, "invalid batch handle");
+  if (!b || !handle_live(b) || b->magic != kBatchMagic) return fail(P2P_ERR_STATE, "invalid batch handle");
   return P2P_OK;
 }
 
+// Waits for the batch's last recorded launch, then releases it.
 void batch_free(p2p_batch_s* b) {
-  (void)hipDeviceSynchronize();
+  handle_remove(b);
+  if (b->last_use) {
+    (void)hipEventSynchronize(b->last_use);
+    (void)hipEventDestroy(b->last_use);
+  }
   for (auto& pr : b->timed) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -64,6 +70,13 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
   b->width = 64;
   b->wpb = 4;
   b->timing = false;
+  b->last_use = nullptr;
+  handle_add(b);
+  if (hipEventCreateWithFlags(&b->last_use, hipEventDisableTiming) != hipSuccess) {
+    b->last_use = nullptr;
+    batch_free(b);
+    return fail(P2P_ERR_HIP, "hipEventCreateWithFlags failed");
+  }
   std::vector<InstDesc> desc(count);
   bool helm = false;
   for (int i = 0; i < count; ++i) {
@@ -139,6 +152,7 @@ p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int
   // and would leave at least half of every wider item idle
   p2p_status rc = run(b, io, m <= 16 ? 16 : (m <= 32 ? 32 : b->width), b->wpb, s, e0, e1);
   if (e0) sink->emplace_back(e0, e1);
+  if (rc == P2P_OK) record_use(b->last_use, s);
   return rc;
 }
 
@@ -177,6 +191,14 @@ static bool cache_lookup(const char* path, const std::string& key, int* width, i
     }
   }
   return false;
+}
+
+void batch_use_cache(p2p_batch_s* b, const char* path) {
+  int width = b->width, wpb = b->wpb;
+  if (cache_lookup(path, tune_key(b), &width, &wpb)) {
+    b->width = width;
+    b->wpb = wpb;
+  }
 }
 
 p2p_status batch_tune(p2p_batch_s* b, const void* const* q, void* const* y, const char* path, hipStream_t s,

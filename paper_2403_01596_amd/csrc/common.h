@@ -16,6 +16,13 @@ namespace p2p {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kIdBits = 21;      // box ids per axis live in [0, 2^21)
 constexpr int kBlock = 256;      // threads per workgroup for the streaming kernels
+// FP32 plans: near pairs whose fixed-point difference is shorter than this many
+// quanta get their kernel value from the FP64 coordinates (see p2p_plan_s).
+// Every other pair is at least 2^20 quanta apart, so the rounding of its
+// coordinates (at most one quantum per axis) perturbs its term by at most
+// sqrt(3) 2^-20 relative.
+constexpr int kCloseBits = 20;
+constexpr int32_t kCloseQuanta = 1 << kCloseBits;
 
 // ---------------------------------------------------------------------------
 // error plumbing
@@ -67,11 +74,27 @@ struct p2p_plan_s {
   int32_t* tile_src;   // [tile_len] sorted position of the source
   double* tile_x64;    // [3][tile_len] (FP64 plans)
   int32_t* tile_x32;   // [3][tile_len] (FP32 plans)
+  // FP32 plans: corrections for the near pairs whose fixed-point coordinate
+  // difference is shorter than kCloseQuanta quanta.  For such a pair the
+  // quantisation of the coordinates is no longer small against the distance, so
+  // each kernel adds, for its target, the exact term (from the FP64 coordinates)
+  // minus the term it computed from the fixed-point ones.  Entries of box T:
+  // [cp_off[T], cp_off[T] + cp_num[T]); cp_num is zero for almost every box.
+  int64_t n_close;     // entries (ordered pairs)
+  int64_t cp_cap;      // capacity of the entry arrays
+  int32_t* cp_num;     // [B]  per box
+  int32_t* cp_off;     // [B]  per box, valid where cp_num > 0
+  int32_t* cp_tgt;     // [cap] sorted position of the target
+  int32_t* cp_src;     // [cap] sorted position of the source
+  float2* cp_g;        // [cap]    exact minus computed (c + i s) / r, quantum units
+  float2* cp_h;        // [3][cap] the same for (c + i s)(i k - 1/r) d / r^2 (reverse pass)
+  void* arena3;        // entry arrays when they outgrow the capacity reserved in arena2
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
   void* g_sorted;      // [n * max_rhs] complex
   // complex64 plans with max_rhs >= 16: the matrix-core path for many right-hand sides
   p2p_batch_s* self_batch;
+  hipEvent_t last_use;  // recorded after each call's work: destroy waits for it
   // diagnostics: event pairs around the sweep kernels
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* timed;
@@ -81,7 +104,21 @@ namespace p2p {
 
 constexpr uint64_t kPlanMagic = 0x7032705f706c616eull;
 
+// Live handles (plans and batches).  A handle is looked up here before it is
+// dereferenced, so a destroyed or foreign pointer is reported as an invalid
+// handle instead of being read.
+void handle_add(const void* h);
+void handle_remove(const void* h);
+bool handle_live(const void* h);
+
+// Records ev on stream s unless s is being captured into a graph (a recorded
+// event there would only be reached by replays): the last call a destroy has to
+// wait for.
+void record_use(hipEvent_t ev, hipStream_t s);
+
 // device memory cache and pinned staging (memory.hip)
+// P2P_TEST_FAIL_ALLOC=n (test hook): the n-th allocation after the variable is set
+// (or changed) fails as if the device were out of memory.
 void* dmem_alloc(size_t bytes);  // current device; nullptr when out of memory
 void dmem_free(void* p);         // the caller guarantees no pending work uses p
 struct StagingLock {

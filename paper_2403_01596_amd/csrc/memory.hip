@@ -5,8 +5,10 @@
 // microseconds each.  Blocks released by the library are kept per device and
 // handed out again for requests they fit; readbacks of the plan build's small
 // status block go through one pinned host buffer per device.
+#include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 
 #include "common.h"
@@ -46,11 +48,32 @@ void release_cached(DeviceCache& c) {
   c.cached = 0;
 }
 
+// P2P_TEST_FAIL_ALLOC=n: the n-th allocation after the variable is set (or given a
+// new value) fails.  Tests drive the out-of-memory paths with it.
+bool injected_failure() {
+  static std::string armed;
+  static long long seen = 0;
+  const char* v = std::getenv("P2P_TEST_FAIL_ALLOC");
+  if (!v || !*v) {
+    armed.clear();
+    return false;
+  }
+  if (armed != v) {
+    armed = v;
+    seen = 0;
+  }
+  return ++seen == std::atoll(v);
+}
+
 }  // namespace
 
 void* dmem_alloc(size_t bytes) {
   const int d = current_device();
   if (d < 0) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (injected_failure()) return nullptr;
+  }
   const size_t want = (std::max<size_t>(bytes, 1) + kGranule - 1) / kGranule * kGranule;
   std::lock_guard<std::mutex> lk(g_mu);
   DeviceCache& c = g_dev[d];

@@ -25,6 +25,12 @@ struct InstDesc {
   float kturns;      // k * 2^qexp / (2 pi)
   float scale;       // 2^-qexp / (4 pi)
   int32_t may_coincide;  // points of distinct boxes may coincide
+  // close-pair corrections (null cp_num: none), as in p2p_plan_s
+  const int32_t* cp_num;
+  const int32_t* cp_off;
+  const int32_t* cp_tgt;
+  const int32_t* cp_src;
+  const float2* cp_g;
 };
 
 // Per-call pointers, passed by value (so that a captured graph holds them).
@@ -65,5 +71,8 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
 p2p_status batch_apply(p2p_batch_s* b, const void* const* q, void* const* y, int m, hipStream_t s, bool timing,
                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* sink);
 void batch_free(p2p_batch_s* b);
+// The launch shape recorded for this batch's workload key in an autotuner cache
+// file, if there is one (no timing).
+void batch_use_cache(p2p_batch_s* b, const char* path);
 
 }  // namespace p2p

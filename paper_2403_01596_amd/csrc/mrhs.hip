@@ -232,6 +232,38 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
     wave_lds_sync();
   }
   // D[row][col]: lane j + 16 (row / 4), register row % 4
+  float re[4][TILES16], im[4][TILES16];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < TILES16; ++q) {
+      re[r][q] = S.p1[q][r] - S.p2[q][r];
+      im[r][q] = S.p3[q][r] - S.p1[q][r] - S.p2[q][r];
+    }
+  // close pairs of the tile's targets (FP32 plans, rare): exact minus computed
+  // kernel value times the source's strengths, added to the target's row
+  if (D.cp_num) {
+    const int32_t nc = ld_uniform(D.cp_num + T);
+    if (nc) {
+      const int32_t c0 = ld_uniform(D.cp_off + T);
+      for (int32_t e = c0; e < c0 + nc; ++e) {
+        const int32_t row = ld_uniform(D.cp_tgt + e) - t_first;
+        if (row < 0 || row >= nt || (row >> 2) != kk) continue;
+        const float2 dg = D.cp_g[e];
+        const float2* qr = qb + (int64_t)D.perm[D.cp_src[e]] * m;
+#pragma unroll
+        for (int q = 0; q < TILES16; ++q) {
+          const float2 v = qr[col[q]];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (r == (row & 3)) {
+              re[r][q] += dg.x * v.x - dg.y * v.y;
+              im[r][q] += dg.x * v.y + dg.y * v.x;
+            }
+        }
+      }
+    }
+  }
   float2* y = io.y[inst];
   const float sc = D.scale;
 #pragma unroll
@@ -242,9 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
 #pragma unroll
       for (int q = 0; q < TILES16; ++q) {
         const int c = rg + i + 16 * q;
-        const float re = S.p1[q][r] - S.p2[q][r];
-        const float im = S.p3[q][r] - S.p1[q][r] - S.p2[q][r];
-        if (c < m) y[yi + c] = make_float2(re * sc, im * sc);
+        if (c < m) y[yi + c] = make_float2(re[r][q] * sc, im[r][q] * sc);
       }
     }
   }
@@ -269,6 +299,13 @@ InstDesc make_desc(const p2p_plan_s* P) {
   d.kturns = (float)(P->k * std::ldexp(1.0, P->qexp) / (2.0 * M_PI));
   d.scale = (float)(std::ldexp(1.0, -P->qexp) / (4.0 * M_PI));
   d.may_coincide = P->may_coincide ? 1 : 0;
+  if (P->n_close > 0) {
+    d.cp_num = P->cp_num;
+    d.cp_off = P->cp_off;
+    d.cp_tgt = P->cp_tgt;
+    d.cp_src = P->cp_src;
+    d.cp_g = P->cp_g;
+  }
   return d;
 }
 

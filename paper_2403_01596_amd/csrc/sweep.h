@@ -175,6 +175,16 @@ struct SweepGeom {
   typename Tr::real kparam;      // F32: turns per quantum; F64: turns per unit length
   typename Tr::coord far;        // x offset of padding entries: farther than any near pair
   bool may_coincide;             // points of distinct boxes may coincide: mask every chunk
+  // F32 plans with close pairs (else cp_num is null): per box, entries
+  // [cp_off[T], cp_off[T] + cp_num[T]) of target, source, and the exact minus the
+  // computed kernel values (cp_h: [3][cp_cap])
+  const int32_t* cp_num;
+  const int32_t* cp_off;
+  const int32_t* cp_tgt;
+  const int32_t* cp_src;
+  const float2* cp_g;
+  const float2* cp_h;
+  int64_t cp_cap;
 };
 
 template <class Tr>
@@ -191,6 +201,14 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
   G.n = P->n;
   G.perm = P->perm;
   G.may_coincide = P->may_coincide;
+  const bool close = std::is_same<Tr, F32>::value && P->n_close > 0;
+  G.cp_num = close ? P->cp_num : nullptr;
+  G.cp_off = P->cp_off;
+  G.cp_tgt = P->cp_tgt;
+  G.cp_src = P->cp_src;
+  G.cp_g = P->cp_g;
+  G.cp_h = P->cp_h;
+  G.cp_cap = P->cp_cap;
   if constexpr (std::is_same<Tr, F32>::value) {
     G.tx = P->tile_x32;
     G.sx = P->sx32;
@@ -309,6 +327,7 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
 //   load_src(p, pay)      payload of the source at sorted position p
 //   load_tgt(t, pay)      payload of the target at sorted position t (uniform)
 //   pair<HELM>(geo, spay, tpay, acc)
+//   correct(G, e, t, acc) F32: add close-pair entry e of target t to its sums
 //   store(t, acc)         final values of target t (sorted position), by its lane
 template <class Tr, class Op, bool HELM, bool CSR>
 __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, SweepLds<Tr, Op, CSR>& L) {
@@ -388,12 +407,21 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
     }
     wave_lds_sync();
-    if (tb + lane < te) {
-      real mine[NA];
+    real mine[NA];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) mine[a] = L.sums[a][lane];
-      op.store(tb + lane, mine);
+    for (int a = 0; a < NA; ++a) mine[a] = L.sums[a][lane];
+    if constexpr (std::is_same<Tr, F32>::value) {
+      // close pairs of the box's targets: exact minus computed terms (rare)
+      if (G.cp_num) {
+        const int32_t nc = ld_uniform(G.cp_num + T);
+        if (nc) {
+          const int32_t c0 = ld_uniform(G.cp_off + T);
+          for (int32_t e = c0; e < c0 + nc; ++e)
+            if (ld_uniform(G.cp_tgt + e) == tb + lane) op.correct(G, e, tb + lane, mine);
+        }
+      }
     }
+    if (tb + lane < te) op.store(tb + lane, mine);
     wave_lds_sync();  // the sums are rewritten by the next block of targets
   }
 }

@@ -48,11 +48,11 @@ def test_argument_errors_before_device_work():
     assert L.p2p_plan_create(dummy, dummy, 5, -1.0, None, None, ctypes.byref(out)) == 2
     assert L.p2p_plan_create(dummy, dummy, 5, float("nan"), None, None, ctypes.byref(out)) == 2
     assert L.p2p_plan_create(dummy, dummy, 10 ** 9, 1.0, None, None, ctypes.byref(out)) == 2
-    bad = p2p._Opts(7, 0, 1, 0)
+    bad = p2p._Opts(7, 0, 1, 0, None)
     assert L.p2p_plan_create(dummy, dummy, 5, 1.0, ctypes.byref(bad), None, ctypes.byref(out)) == 1
-    bad = p2p._Opts(1, 0, 0, 0)
+    bad = p2p._Opts(1, 0, 0, 0, None)
     assert L.p2p_plan_create(dummy, dummy, 5, 1.0, ctypes.byref(bad), None, ctypes.byref(out)) == 1
-    bad = p2p._Opts(1, 0, 1, 4)
+    bad = p2p._Opts(1, 0, 1, 4, None)
     assert L.p2p_plan_create(dummy, dummy, 5, 1.0, ctypes.byref(bad), None, ctypes.byref(out)) == 1
     assert out.value is None
     # invalid handles
@@ -60,6 +60,8 @@ def test_argument_errors_before_device_work():
     assert L.p2p_apply_backward(None, None, None, None, None, 1, 1, None) == 6
     assert L.p2p_plan_info(None, None) == 6
     assert L.p2p_plan_destroy(None) == 0
+    assert L.p2p_batch_destroy(None) == 0
+
     origin = (ctypes.c_double * 3)(0, 0, 0)
     assert L.p2p_box_ids(None, -1, origin, 1.0, None, None) == 1
     assert L.p2p_box_ids(dummy, 5, origin, 0.0, dummy, None) == 2
@@ -76,6 +78,21 @@ def test_argument_errors_before_device_work():
     assert L.p2p_plan_create_grid(dummy, 5, origin, 1.0, 1.0, None, None, None) == 1
     assert out.value is None
 
+
+def test_foreign_handles_are_not_read():
+    # pointers that were never handed out by the library (as a destroyed handle
+    # would be): looked up among the live handles, so nothing is dereferenced
+    L = p2p.lib()
+    for h in (ctypes.c_void_p(16), ctypes.c_void_p(0xdead0000), ctypes.c_void_p(ctypes.addressof(ctypes.c_int64(7)))):
+        assert L.p2p_plan_destroy(h) == 6
+        assert L.p2p_apply(h, None, None, 1, 1, None) == 6
+        assert L.p2p_apply_backward(h, None, None, None, None, 1, 1, None) == 6
+        assert L.p2p_plan_info(h, None) == 6
+        assert L.p2p_plan_export(h, None, None, None, None, None) == 6
+        assert L.p2p_plan_timing(h, 1) == 6
+        assert L.p2p_batch_destroy(h) == 6
+        assert L.p2p_batch_apply(h, None, None, None) == 6
+        assert b"invalid" in L.p2p_last_error()
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(p2p, "_lib", None)

@@ -1,0 +1,139 @@
+"""Close pairs in the FP32 path: planted pairs at r = 2^-k h, compared row by row.
+
+The FP32 kernels take coordinate differences from fixed-point coordinates whose
+quantum is about 2^-29 h; a pair a few quanta apart would carry a large relative
+error in its term, and such a term dominates its row.  Every near pair closer
+than 2^20 quanta is therefore corrected from the FP64 coordinates at plan time.
+These tests plant pairs at r = 2^-k h for k = 8 .. 40 in a 200k-point ellipsoid
+(64 points per box, box = a quarter wavelength, the density sweep's densest
+case): inside one box, and straddling a box face (where the two points are in
+different boxes).  The pairs below one quantum (k >= 30) sit on one fixed-point
+position across a face, the case where an uncorrected kernel divides by zero.
+Every planted row is compared with the FP64 oracle on its own, and the whole
+output too.  Forward (both layouts), reverse pass and the matrix-core path.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_01596_amd as p2p
+import workloads as W
+from gpu_helpers import dev, rel_l2
+
+pytestmark = pytest.mark.gpu
+KS = list(range(8, 41))
+
+
+def planted(seed=3):
+    """The ellipsoid plus planted pairs; returns (xyz, ids, q, k, h, rows of planted points)."""
+    base = W.ellipsoid(200_000, 64, seed=seed, dtype=np.complex64)
+    rng = np.random.default_rng(seed)
+    h, o = base.h, base.origin
+    pts, rows = [base.xyz], []
+    n = base.n
+    anchors = rng.choice(n, 2 * len(KS), replace=False)
+    for j, kk in enumerate(KS):
+        r = h * 2.0 ** -kk
+        # inside a box: a partner r away in a random direction, same box
+        a = base.xyz[anchors[2 * j]]
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        b = a + r * u
+        if np.any(np.floor((b - o) / h) != np.floor((a - o) / h)):
+            b = a - r * u
+        # across a face: two points r apart around the x face of another anchor's box
+        c = base.xyz[anchors[2 * j + 1]].copy()
+        face = o[0] + (np.floor((c[0] - o[0]) / h) + 1) * h
+        c1, c2 = c.copy(), c.copy()
+        c1[0] = face - r / 2
+        c2[0] = face + r / 2
+        pts.append(np.stack([b, c1, c2]))
+        rows += [anchors[2 * j], n + 3 * j, n + 3 * j + 1, n + 3 * j + 2]
+    xyz = np.ascontiguousarray(np.concatenate(pts))
+    ids = W.leaf_ids(xyz, o, h)
+    q = W.strengths(xyz.shape[0], 1, rng, np.complex64)
+    return xyz, ids, q, base.k, h, np.array(rows)
+
+
+@pytest.fixture(scope="module")
+def case():
+    xyz, ids, q, k, h, rows = planted()
+    orc = oracle.Plan(ids)
+    yref = orc.apply(xyz, k, q)
+    print("planted: %d points, %d planted rows" % (xyz.shape[0], rows.size), flush=True)
+    return xyz, ids, q, k, h, rows, orc, yref
+
+
+def row_errors(got, ref, rows):
+    g, r = got[rows].reshape(rows.size, -1), ref[rows].reshape(rows.size, -1)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+
+
+def test_planted_rows_cross_the_face(case):
+    xyz, ids, q, k, h, rows, orc, yref = case
+    # the face pairs really straddle the face: distinct boxes, adjacent along x
+    face = rows.reshape(-1, 4)[:, 2:]
+    assert np.all(ids[face[:, 1], 0] == ids[face[:, 0], 0] + 1)
+
+
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+def test_forward_planted(case, layout):
+    xyz, ids, q, k, h, rows, orc, yref = case
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout=layout)
+    info = P.info()
+    y = P.apply(dev(q)).cpu().numpy().reshape(-1, 1)
+    assert np.isfinite(y).all()
+    e_rows = row_errors(y, yref, rows)
+    e_all = rel_l2(y, yref)
+    print("  %s: %d close pairs, quantum 2^%d (h 2^%.1f); planted rows: max %.2e; whole %.2e" % (
+        layout, info["n_close_pairs"], info["quantum_exp"], math.log2(h), e_rows.max(), e_all), flush=True)
+    assert info["n_close_pairs"] >= 4 * len(KS)
+    assert e_rows.max() <= 1e-5
+    assert e_all <= 1e-6
+    P.close()
+
+
+def test_backward_planted(case):
+    xyz, ids, q, k, h, rows, orc, yref = case
+    g = W.strengths(xyz.shape[0], 1, np.random.default_rng(9), np.complex64)
+    dq_ref, dx_ref = orc.backward(xyz, k, q, g)
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout="csr")
+    dq, dx = P.backward(dev(q), dev(g))
+    dq, dx = dq.cpu().numpy().reshape(-1, 1), dx.cpu().numpy()
+    assert np.isfinite(dq).all() and np.isfinite(dx).all()
+    eq, ex = row_errors(dq, dq_ref, rows), row_errors(dx, dx_ref, rows)
+    print("  reverse pass, planted rows: dq max %.2e, dx max %.2e; whole dq %.2e dx %.2e" % (
+        eq.max(), ex.max(), rel_l2(dq, dq_ref), rel_l2(dx, dx_ref)), flush=True)
+    assert eq.max() <= 1e-5 and ex.max() <= 1e-5
+    assert rel_l2(dq, dq_ref) <= 1e-6 and rel_l2(dx, dx_ref) <= 1e-5
+    P.close()
+
+
+def test_matrix_cores_planted(case):
+    xyz, ids, q, k, h, rows, orc, yref = case
+    m = 16
+    qm = W.strengths(xyz.shape[0], m, np.random.default_rng(11), np.complex64)
+    ref = orc.apply(xyz, k, qm)
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout="csr",
+                 max_rhs=m)
+    y = P.apply(dev(qm)).cpu().numpy()
+    assert np.isfinite(y).all()
+    e_rows = row_errors(y, ref, rows)
+    print("  matrix cores, %d columns: planted rows max %.2e, whole %.2e" % (m, e_rows.max(), rel_l2(y, ref)),
+          flush=True)
+    assert e_rows.max() <= 1e-5 and rel_l2(y, ref) <= 1e-6
+    P.close()
+
+
+def test_f64_planted(case):
+    xyz, ids, q, k, h, rows, orc, yref = case
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex128, layout="csr")
+    y = P.apply(dev(q.astype(np.complex128))).cpu().numpy().reshape(-1, 1)
+    e_rows = row_errors(y, yref, rows)
+    print("  FP64: planted rows max %.2e, whole %.2e" % (e_rows.max(), rel_l2(y, yref)), flush=True)
+    assert e_rows.max() <= 1e-12 and rel_l2(y, yref) <= 1e-12
+    assert P.info()["n_close_pairs"] == 0
+    P.close()

@@ -2,9 +2,10 @@
 FP64 oracle.
 
 - 4M points on the (1, 0.5, 0.25) ellipsoid at 16, 32 and 64 points per box with
-  k = pi / (2h), both layouts, FP32: pair counts exact, sampled rows row by row;
+  k = pi / (2h), both layouts, FP32: pair counts exact, every row of the output;
 - the multi-right-hand-side batch (1M sphere points plus 16 uneven instances,
-  64 columns each) in one tuned launch: sampled rows of every instance;
+  64 columns each) in one tuned launch: every row of the 1M instance; for the 16
+  small ones sampled rows plus the rows of each instance's closest pairs;
 - the 500k-point cube's reverse pass (dq and dx), FP32 and FP64, against the
   oracle's full reverse pass, and its FP64 dx against central differences (step
   1e-3, and a Richardson step) of the loss sum |y|^2 computed on the GPU;
@@ -29,25 +30,36 @@ pytestmark = pytest.mark.gpu
 TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
 
 
+def closest_rows(xyz, count):
+    """Rows of the points with the closest neighbours (both points of each pair)."""
+    from scipy.spatial import cKDTree
+
+    d, j = cKDTree(xyz).query(xyz, k=2)
+    order = np.argsort(d[:, 1])[:count]
+    return np.unique(np.concatenate([order, j[order, 1]]))
+
+
 @pytest.mark.parametrize("d", [16, 32, 64])
 def test_ellipsoid_4m(d):
     inst = W.ellipsoid_4m(d)
     print("ellipsoid 4M D=%d generated" % d, flush=True)
     orc = oracle.Plan(inst.ids)
     st = orc.stats(inst.xyz)
-    rows = np.random.default_rng(d).choice(inst.n, 1500, replace=False)
-    yref = orc.apply_rows(inst.xyz, inst.k, inst.q, rows)
+    yref = orc.apply(inst.xyz, inst.k, inst.q)
+    print("  oracle done", flush=True)
+    close = closest_rows(inst.xyz, 200)
     xyz, ids, q = dev(inst.xyz, torch.float64), dev(inst.ids, torch.int32), dev(inst.q)
     for layout in ("tiles", "csr"):
         P = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=layout)
         info = P.info()
         assert info["n_boxes"] == orc.n_boxes and info["n_nbr"] == orc.n_nbr
         assert info["n_pairs"] == st["n_pairs"] and info["t_max"] == st["t_max"]
-        y = P.apply(q)
-        torch.cuda.synchronize()
-        err = rel_l2(y.cpu().numpy()[rows], yref)
-        print("  %s: %d pairs, rel L2 on sampled rows %.3e" % (layout, info["n_pairs"], err), flush=True)
-        assert err <= TOL[torch.complex64]
+        y = P.apply(q).cpu().numpy()
+        err = rel_l2(y, yref)
+        err_close = rel_l2(y[close], yref[close])
+        print("  %s: %d pairs, %d close-pair entries, rel L2 over every row %.3e, closest-pair rows %.3e" % (
+            layout, info["n_pairs"], info["n_close_pairs"], err, err_close), flush=True)
+        assert err <= TOL[torch.complex64] and err_close <= TOL[torch.complex64]
         P.close()
 
 
@@ -66,14 +78,20 @@ def test_multi_rhs_batch_full(tmp_path):
     torch.cuda.synchronize()
     worst = 0.0
     for j, (inst, y) in enumerate(zip(insts, ys)):
-        rows = np.random.default_rng(j).choice(inst.n, min(inst.n, 300), replace=False)
-        ref = oracle.Plan(inst.ids).apply_rows(inst.xyz, inst.k, inst.q, rows)
         got = y.cpu().numpy()
         assert np.isfinite(got).all()
-        err = rel_l2(got[rows], ref)
+        if j == 0:  # the 1M instance: every row
+            ref = oracle.Plan(inst.ids).apply(inst.xyz, inst.k, inst.q)
+            err = rel_l2(got, ref)
+            print("  1M instance, %d columns, every row: rel L2 %.3e" % (m, err), flush=True)
+        else:
+            rows = np.unique(np.concatenate([np.random.default_rng(j).choice(inst.n, min(inst.n, 300), replace=False),
+                                             closest_rows(inst.xyz, 20)]))
+            ref = oracle.Plan(inst.ids).apply_rows(inst.xyz, inst.k, inst.q, rows)
+            err = rel_l2(got[rows], ref)
         worst = max(worst, err)
         assert err <= TOL[torch.complex64], (j, inst.n, err)
-    print("  worst per-instance rel L2 on sampled rows %.3e" % worst, flush=True)
+    print("  worst per-instance rel L2 %.3e" % worst, flush=True)
     B.close()
     for pl in plans:
         pl.close()
