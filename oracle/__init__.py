@@ -64,6 +64,8 @@ def _load():
     L.orc_apply_rows.argtypes = [P, P, f64, P, ctypes.c_int, P, i64, P, ctypes.c_int]
     L.orc_backward.argtypes = [P, P, f64, P, P, ctypes.c_int, P, P, ctypes.c_int]
     L.orc_dual_dx.argtypes = [P, P, f64, P, ctypes.c_int, i64, ctypes.c_int, P]
+    L.orc2d_apply.argtypes = [P, P, i64, i32, P, ctypes.c_int]
+    L.orc2d_stats.argtypes = [P, i64, i32, P, P, P, P]
     _lib = L
     return L
 
@@ -181,3 +183,24 @@ class Plan:
             S = t["nbr_idx"][e]
             rows.append(t["perm"][t["box_start"][S]:t["box_start"][S + 1]])
         return np.concatenate(rows)
+
+
+# ----------------------------------------------------------------------------
+# the paper's two-dimensional setting (a quadtree over the unit square)
+# ----------------------------------------------------------------------------
+def apply2d(xy: np.ndarray, q: np.ndarray, level: int, threads: int = 0) -> np.ndarray:
+    """y_i = sum over the nine boxes around i's leaf box (quadtree of height level on
+    the unit square), x_j != x_i, of -ln|x_i - x_j| / (2 pi) q_j; q, y real."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    qq = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    y = np.empty(xy.shape[0], np.float64)
+    _check(_load().orc2d_apply(_ptr(xy), _ptr(qq), xy.shape[0], int(level), _ptr(y), threads), "orc2d_apply")
+    return y
+
+
+def stats2d(xy: np.ndarray, level: int) -> dict:
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_load().orc2d_stats(_ptr(xy), xy.shape[0], int(level), ctypes.byref(a), ctypes.byref(b),
+                               ctypes.byref(c), ctypes.byref(d)), "orc2d_stats")
+    return dict(n_pairs=a.value, n_zero_pairs=b.value, t_max=c.value, n_boxes=d.value)
