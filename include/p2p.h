@@ -216,6 +216,71 @@ p2p_status p2p_batch_destroy(p2p_batch batch);
  * allocation after the variable is set (or changed) fail that way, for tests. */
 p2p_status p2p_plan_destroy(p2p_plan plan);
 
+/* ---- The paper's own experiment in two dimensions (sections 3.1-3.3, 4.6) ----
+ * Points of the unit square (the paper's plate), a quadtree of height L whose
+ * 4^(L-1) leaf boxes are (floor(x 2^(L-1)), floor(y 2^(L-1))), the nine neighbour
+ * boxes (the box itself included), one real potential per source, and the 2-D
+ * potential G(r) = -ln(r) / (2 pi), the reading taken of the kernel the paper
+ * names without writing it:
+ *     y_i = sum over j in the nine boxes around i's box, x_j != x_i, of G(|x_i - x_j|) q_j.
+ * The paper's two GPU layouts, each collected on the host, copied to the device
+ * and swept by its own kernel, with the three phases timed separately:
+ *   P2P2D_INDEXING   (section 3.2): seven arrays stored one after the other --
+ *                    target and source coordinates, the targets of every box in
+ *                    Morton order and their box offsets, the neighbour sources of
+ *                    every box and their offsets, the source potentials; one
+ *                    thread per box, every box of the tree (empty ones included);
+ *   P2P2D_REPETITION (section 3.3): one record per target, [x, y, count, then x,
+ *                    y and potential of each neighbour source], all records of
+ *                    one length, 3 + 27 CT doubles (eq. 8), or 3 + 3 times the
+ *                    largest neighbourhood when boxes hold more than CT points;
+ *                    one thread per target.  A target-index array (one int per
+ *                    target) maps records to output rows.
+ * Morton key of a box: bit 2b from bit b of its x index, 2b+1 from its y index.
+ * Host arrays: xy [n, 2] float64, q [n] float64; y: device [n] float64, in the
+ * caller's point order.  A point outside [0, 1)^2 gives P2P_ERR_RANGE. */
+typedef enum { P2P2D_INDEXING = 0, P2P2D_REPETITION = 1 } p2p2d_method;
+typedef struct p2p2d_s* p2p2d;
+typedef struct {
+  int64_t n_points;
+  int64_t n_boxes;        /* 4^(L-1), empty boxes included                          */
+  int64_t layout_bytes;   /* the collected layout                                   */
+  int64_t n_slots;        /* ordered near pairs, self pairs included                */
+  int64_t n_src_entries;  /* Indexing: neighbour-source entries over all boxes      */
+  int32_t t_max;          /* largest box occupancy                                  */
+  int32_t record_len;     /* Repetition: doubles per record                         */
+  double collect_ms;      /* host collection (p2p2d_collect)                        */
+  double transfer_ms;     /* host-to-device copy (last p2p2d_transfer)              */
+} p2p2d_info_t;
+/* Host collection of the method's layout (single-threaded, as the paper's). level
+ * in [1, 15]; ct >= 1 (the clustering threshold of section 3.1, which sizes the
+ * Repetition records). */
+p2p_status p2p2d_collect(p2p2d_method method, const double* xy, const double* q, int64_t n, int32_t level,
+                         int32_t ct, p2p2d* out);
+/* Copies the layout to the device (allocating device memory on first use) and
+ * waits for the copy. */
+p2p_status p2p2d_transfer(p2p2d h, void* stream);
+/* The method's kernel: y = the near-field potentials.  Asynchronous on stream. */
+p2p_status p2p2d_run(p2p2d h, double* y, void* stream);
+p2p_status p2p2d_info(p2p2d h, p2p2d_info_t* out);
+/* Diagnostics: the collected host layout (valid until p2p2d_destroy) and the byte
+ * offsets within it of, in order: target coordinates, source coordinates, target
+ * indices, their box offsets, neighbour-source indices, their box offsets, source
+ * potentials (Indexing), records, record target indices (Repetition); offsets of
+ * the other method's arrays are 0.  Host only. */
+p2p_status p2p2d_layout(p2p2d h, const void** data, int64_t* bytes, int64_t* offsets);
+/* Frees the handle after its last run has finished; NULL is a no-op, a handle
+ * that is not live gives P2P_ERR_STATE. */
+p2p_status p2p2d_destroy(p2p2d h);
+
+/* The same 2-D near field by this library's own route: a complex128 (FP64) plan
+ * of the points (x, y, 0) with ids (floor(x 2^(L-1)), floor(y 2^(L-1)), 0) -- for
+ * instance p2p_plan_create_grid with origin 0 and h = 2^(1-L) -- whose boxes are
+ * the quadtree's in the same Morton order, swept one wavefront per box with the
+ * kernel -ln(r) / (2 pi).  q, y: device [n] float64 in the caller's order.  The
+ * plan's own (Helmholtz) k is not used.  Asynchronous on stream. */
+p2p_status p2p_apply_log2d(p2p_plan plan, const double* q, double* y, void* stream);
+
 const char* p2p_status_str(p2p_status s);
 const char* p2p_last_error(void);
 

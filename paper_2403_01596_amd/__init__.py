@@ -46,6 +46,12 @@ class _Info(ctypes.Structure):
                 ("n_close_pairs", ctypes.c_int64)]
 
 
+class _Info2D(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int64), ("layout_bytes", ctypes.c_int64),
+                ("n_slots", ctypes.c_int64), ("n_src_entries", ctypes.c_int64), ("t_max", ctypes.c_int32),
+                ("record_len", ctypes.c_int32), ("collect_ms", ctypes.c_double), ("transfer_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -75,13 +81,21 @@ def lib():
     L.p2p_batch_destroy.argtypes = [P]
     L.p2p_plan_timing.argtypes = [P, ctypes.c_int]
     L.p2p_plan_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.p2p2d_collect.argtypes = [ctypes.c_int, P, P, i64, i32, i32, ctypes.POINTER(ctypes.c_void_p)]
+    L.p2p2d_transfer.argtypes = [P, P]
+    L.p2p2d_run.argtypes = [P, P, P]
+    L.p2p2d_info.argtypes = [P, ctypes.POINTER(_Info2D)]
+    L.p2p2d_destroy.argtypes = [P]
+    L.p2p2d_layout.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(i64), P]
+    L.p2p_apply_log2d.argtypes = [P, P, P, P]
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
     for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
                  "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
                  "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
-                 "p2p_batch_timing_read", "p2p_batch_destroy"):
+                 "p2p_batch_timing_read", "p2p_batch_destroy", "p2p2d_collect", "p2p2d_transfer", "p2p2d_run",
+                 "p2p2d_info", "p2p2d_destroy", "p2p_apply_log2d", "p2p2d_layout"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -207,6 +221,16 @@ class Plan:
             if xyz.shape != src.shape or xyz.device != src.device or not torch.equal(xyz.detach(), src.detach()):
                 raise ValueError("xyz differs from the positions this plan was built from; build a new plan")
 
+    def apply_log2d(self, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The paper's 2-D potential -ln(r) / (2 pi) over this plan's near pairs (points in
+        the plane z = 0 with quadtree ids (bx, by, 0)); q real float64 [n].  FP64 plans."""
+        q = _cuda(q, torch.float64, "q")
+        if q.shape != (self.n,):
+            raise ValueError("q must be [n]")
+        y = torch.empty_like(q) if out is None else out
+        _check(lib().p2p_apply_log2d(self.handle, _ptr(q), _ptr(y), _stream()))
+        return y
+
     def timing(self, enable: bool = True):
         """Record HIP events around the sweep kernels of later apply/backward calls."""
         _check(lib().p2p_plan_timing(self.handle, 1 if enable else 0))
@@ -317,6 +341,72 @@ class Batch:
 
 def apply(plan: Plan, q: torch.Tensor) -> torch.Tensor:
     return plan.apply(q)
+
+
+METHODS_2D = {"indexing": 0, "repetition": 1}
+
+
+class Quad2D:
+    """One of the paper's two GPU layouts for its 2-D experiment (sections 3.2, 3.3):
+    collected on the host from host arrays, copied to the device, swept by its own
+    kernel.  xy: numpy float64 [n, 2] in the unit square; q: numpy float64 [n]."""
+
+    def __init__(self, method: str, xy, q, level: int, ct: int = 15):
+        import numpy as np
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+        if self.xy.ndim != 2 or self.xy.shape[1] != 2 or self.q.shape[0] != self.xy.shape[0]:
+            raise ValueError("xy must be [n, 2] and q [n]")
+        self.n = self.xy.shape[0]
+        h = ctypes.c_void_p()
+        _check(lib().p2p2d_collect(METHODS_2D[method], ctypes.c_void_p(self.xy.ctypes.data),
+                                   ctypes.c_void_p(self.q.ctypes.data), self.n, int(level), int(ct), ctypes.byref(h)))
+        self._h = h
+
+    def transfer(self):
+        _check(lib().p2p2d_transfer(self._h, _stream()))
+
+    def run(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        y = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
+        _check(lib().p2p2d_run(self._h, _ptr(y), _stream()))
+        return y
+
+    def info(self) -> dict:
+        inf = _Info2D()
+        _check(lib().p2p2d_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _Info2D._fields_}
+
+    def layout(self) -> dict:
+        """The collected host layout as numpy views (a copy), by array name."""
+        import numpy as np
+        data, nbytes = ctypes.c_void_p(), ctypes.c_int64()
+        offs = (ctypes.c_int64 * 9)()
+        _check(lib().p2p2d_layout(self._h, ctypes.byref(data), ctypes.byref(nbytes), offs))
+        raw = np.ctypeslib.as_array((ctypes.c_char * nbytes.value).from_address(data.value)).view(np.uint8).copy()
+        inf = self.info()
+        n, B = inf["n_points"], inf["n_boxes"]
+
+        def arr(i, dt, count):
+            return raw[offs[i]:offs[i] + np.dtype(dt).itemsize * count].view(dt)
+
+        if inf["record_len"] == 0:
+            return dict(target_xy=arr(0, np.float64, 2 * n).reshape(n, 2), source_xy=arr(1, np.float64, 2 * n).reshape(n, 2),
+                        target_idx=arr(2, np.int32, n), target_start=arr(3, np.int32, B + 1),
+                        source_idx=arr(4, np.int32, inf["n_src_entries"]), source_start=arr(5, np.int32, B + 1),
+                        q=arr(6, np.float64, n))
+        R = inf["record_len"]
+        return dict(records=arr(7, np.float64, n * R).reshape(n, R), record_target=arr(8, np.int32, n))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.p2p2d_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class P2PFunction(torch.autograd.Function):

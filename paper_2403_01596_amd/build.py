@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp2p.so")
-SOURCES = ["api.hip", "memory.hip", "plan.hip", "apply.hip", "backward.hip", "mrhs.hip", "batch.hip"]
+SOURCES = ["api.hip", "memory.hip", "plan.hip", "apply.hip", "backward.hip", "mrhs.hip", "batch.hip",
+           "quad2d.hip"]
 ARCH = os.environ.get("P2P_OFFLOAD_ARCH", "gfx950")
 
 

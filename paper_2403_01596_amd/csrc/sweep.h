@@ -155,6 +155,30 @@ struct F64 {
   }
 };
 
+// The paper's two-dimensional potential, G(r) = -ln(r) / (2 pi) = -ln(r^2) / (4 pi),
+// in FP64 on points of a plane (z equal for all points, so dz = 0).  geo() leaves
+// ln(r^2) in l (zero for a masked pair at distance zero); the operation scales.
+struct L2D {
+  using coord = double;
+  using real = double;
+  using cplx = double2;
+  static constexpr int K = 4, K1 = 8;
+  struct Geo {
+    double dx, dy, dz, l;
+  };
+  template <bool HELM, bool MASK>
+  __device__ static __forceinline__ Geo geo(double tx, double ty, double tz, double sx, double sy, double sz,
+                                            double) {
+    Geo g;
+    g.dx = tx - sx;
+    g.dy = ty - sy;
+    g.dz = tz - sz;
+    const double r2 = __builtin_fma(g.dz, g.dz, __builtin_fma(g.dy, g.dy, g.dx * g.dx));
+    g.l = MASK ? ((r2 > 0.0) ? log(r2) : 0.0) : log(r2);
+    return g;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // geometry arguments common to every sweep
 // ---------------------------------------------------------------------------
