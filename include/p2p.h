@@ -93,8 +93,9 @@ typedef struct {
   int32_t quantum_exp;  /* FP32 plans: coordinates are integers in units of 2^e    */
   double d_mean;        /* n_points / n_boxes                                      */
   double max_sep;       /* largest per-axis coordinate difference of a near pair   */
-  int64_t n_close_pairs; /* FP32 plans: ordered near pairs closer than 2^20 quanta,
-                            whose kernel values come from the FP64 coordinates     */
+  int64_t n_close_pairs; /* FP32 plans: ordered near pairs closer than 2^20 quanta
+                            (r != 0), whose kernel values the kernels take from the
+                            FP64 coordinates; 0 for FP64 plans                     */
 } p2p_info;
 
 /* Leaf-box ids from positions: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h),
@@ -126,8 +127,8 @@ p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* orig
                                 const p2p_opts* opts, void* stream, p2p_plan* out);
 
 /* Plan statistics (paper section 3.2: t, the largest box occupancy; section 3.4.1:
- * D, the mean number of points per box).  n_pairs and n_zero_pairs are counted on
- * the device the first time they are asked for (synchronously). */
+ * D, the mean number of points per box).  n_pairs, n_zero_pairs and n_close_pairs
+ * are counted on the device the first time they are asked for (synchronously). */
 p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out);
 
 /* Copies the plan's tables to host memory (any pointer may be NULL): the boxes in

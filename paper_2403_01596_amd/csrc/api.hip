@@ -104,7 +104,6 @@ static p2p_status free_plan(p2p_plan_s* P) {
   delete P->timed;
   dmem_free(P->arena);
   dmem_free(P->arena2);
-  dmem_free(P->arena3);
   if (cur != P->device) (void)hipSetDevice(cur);
   P->magic = 0;
   delete P;
@@ -175,6 +174,7 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   P->max_rhs = o.max_rhs;
   P->n_pairs = -1;
   P->n_zero = -1;
+  P->n_close = -1;
   P->timed = new (std::nothrow) std::vector<std::pair<hipEvent_t, hipEvent_t>>();
   if (!P->timed) {
     delete P;

@@ -57,18 +57,6 @@ struct FwdOp {
       }
     }
   }
-  // Close pair e (FP32 plans): its exact minus computed kernel value times the
-  // source's strengths.
-  __device__ __forceinline__ void correct(const SweepGeom<Tr>& G, int32_t e, int32_t, real* acc) const {
-    const float2 d = G.cp_g[e];
-    const int64_t p = G.cp_src[e];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const cplx q = qs[p * m + col + c];
-      acc[2 * c] += d.x * q.x - d.y * q.y;
-      acc[2 * c + 1] += d.x * q.y + d.y * q.x;
-    }
-  }
   __device__ __forceinline__ void store(int32_t t, const real* a) const {
     const int64_t i = perm[t];
 #pragma unroll

@@ -103,34 +103,6 @@ struct BwdOp {
       acc[OX + 2] = fma(w, G.dz, acc[OX + 2]);
     }
   }
-  // Close pair e (FP32 plans): the exact minus computed values of conj(G) for dq,
-  // and of (c + i s)(i k - 1/r) d / r^2 for dx, applied as in pair().
-  __device__ __forceinline__ void correct(const SweepGeom<Tr>& G, int32_t e, int32_t t, real* acc) const {
-    const int64_t p = G.cp_src[e];
-    if (DQ) {
-      const float2 d = G.cp_g[e];
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const cplx g = gs[p * m + col + c];
-        acc[2 * c] += d.x * g.x + d.y * g.y;
-        acc[2 * c + 1] += d.x * g.y - d.y * g.x;
-      }
-    }
-    if (DX) {
-      const float2 h0 = G.cp_h[e], h1 = G.cp_h[G.cp_cap + e], h2 = G.cp_h[2 * G.cp_cap + e];
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const cplx qs_ = qs[p * m + col + c], gs_ = gs[p * m + col + c];
-        const cplx qt = qs[(int64_t)t * m + col + c], gt = gs[(int64_t)t * m + col + c];
-        // u = conj(g_i) q_j + conj(g_j) q_i
-        const real ur = gt.x * qs_.x + gt.y * qs_.y + gs_.x * qt.x + gs_.y * qt.y;
-        const real ui = gt.x * qs_.y - gt.y * qs_.x + gs_.x * qt.y - gs_.y * qt.x;
-        acc[OX + 0] += h0.x * ur - h0.y * ui;
-        acc[OX + 1] += h1.x * ur - h1.y * ui;
-        acc[OX + 2] += h2.x * ur - h2.y * ui;
-      }
-    }
-  }
   __device__ __forceinline__ void store(int32_t t, const real* a) const {
     const int64_t i = perm[t];
     if (DQ) {

@@ -74,21 +74,13 @@ struct p2p_plan_s {
   int32_t* tile_src;   // [tile_len] sorted position of the source
   double* tile_x64;    // [3][tile_len] (FP64 plans)
   int32_t* tile_x32;   // [3][tile_len] (FP32 plans)
-  // FP32 plans: corrections for the near pairs whose fixed-point coordinate
-  // difference is shorter than kCloseQuanta quanta.  For such a pair the
-  // quantisation of the coordinates is no longer small against the distance, so
-  // each kernel adds, for its target, the exact term (from the FP64 coordinates)
-  // minus the term it computed from the fixed-point ones.  Entries of box T:
-  // [cp_off[T], cp_off[T] + cp_num[T]); cp_num is zero for almost every box.
-  int64_t n_close;     // entries (ordered pairs)
-  int64_t cp_cap;      // capacity of the entry arrays
-  int32_t* cp_num;     // [B]  per box
-  int32_t* cp_off;     // [B]  per box, valid where cp_num > 0
-  int32_t* cp_tgt;     // [cap] sorted position of the target
-  int32_t* cp_src;     // [cap] sorted position of the source
-  float2* cp_g;        // [cap]    exact minus computed (c + i s) / r, quantum units
-  float2* cp_h;        // [3][cap] the same for (c + i s)(i k - 1/r) d / r^2 (reverse pass)
-  void* arena3;        // entry arrays when they outgrow the capacity reserved in arena2
+  // FP32 plans: per box, nonzero if the bounding box of some other neighbour box
+  // comes within kCloseQuanta + 2 quanta of the box's own on every axis.  Only
+  // such boxes can hold a pair of distinct boxes whose fixed-point difference is
+  // shorter than kCloseQuanta quanta; the kernels take the geometry of those pairs
+  // (and of close pairs inside a box) from the FP64 coordinates.
+  int32_t* near;       // [B]
+  int64_t n_close;     // ordered near pairs closer than kCloseQuanta quanta, -1 until counted
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
   void* g_sorted;      // [n * max_rhs] complex

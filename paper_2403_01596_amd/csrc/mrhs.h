@@ -25,12 +25,11 @@ struct InstDesc {
   float kturns;      // k * 2^qexp / (2 pi)
   float scale;       // 2^-qexp / (4 pi)
   int32_t may_coincide;  // points of distinct boxes may coincide
-  // close-pair corrections (null cp_num: none), as in p2p_plan_s
-  const int32_t* cp_num;
-  const int32_t* cp_off;
-  const int32_t* cp_tgt;
-  const int32_t* cp_src;
-  const float2* cp_g;
+  // close pairs, as in p2p_plan_s: per-box near flags, and the FP64 coordinates
+  // their differences come from
+  const int32_t* near;
+  const double* sx64;    // [3][n] FP64 coordinates, sorted order
+  double qinv;           // 2^-qexp
 };
 
 // Per-call pointers, passed by value (so that a captured graph holds them).

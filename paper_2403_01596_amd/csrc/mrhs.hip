@@ -39,14 +39,15 @@ constexpr int kGroupSrc = 512;   // LDS slots per wavefront for staged neighbour
 constexpr int kGroupCap = kGroupSrc - 2 * kStepSrc;  // real entries per group (the rest: padding)
 
 // A group's neighbourhood entries into the wavefront's LDS: {x, y, z, r} with r the
-// source's row in the caller's array (FAST: its byte offset, row * m * 8).  Entries
+// source's row in the caller's array (FAST: its byte offset, row * m * 8), and in
+// pos the source's sorted position (read only for close pairs).  Entries
 // [sg, ge) of box T's list: CSR walks the box's own points first, then its
 // neighbour boxes; TILES copies the box's replicated list.  The slots from ge - sg
 // to 8 past the next multiple of 8 repeat the first entry, so that steps and the
 // prefetch of the step after the last never read a slot that was not written.
 template <bool CSR, bool FAST>
 __device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, const InstDesc& D, int64_t n, int m,
-                                            int4* ent, int lane) {
+                                            int4* ent, int32_t* pos, int lane) {
   const uint32_t rs = FAST ? 8u * (uint32_t)m : 1u;
   if (CSR) {
     int32_t off = 0;
@@ -60,18 +61,25 @@ __device__ __forceinline__ void stage_group(int32_t T, int32_t sg, int32_t ge, c
         const int32_t p = a + (e - off);
         ent[e - sg] = make_int4(ld_global(D.sx32 + p), ld_global(D.sx32 + n + p), ld_global(D.sx32 + 2 * n + p),
                                 (int32_t)((uint32_t)ld_global(D.perm + p) * rs));
+        pos[e - sg] = p;
       }
       off += len;
     }
   } else {
     const int64_t tl = D.tl;
-    for (int32_t e = sg + lane; e < ge; e += kWave)
+    for (int32_t e = sg + lane; e < ge; e += kWave) {
+      const int32_t p = ld_global(D.tsrc + e);
       ent[e - sg] = make_int4(ld_global(D.tx32 + e), ld_global(D.tx32 + tl + e), ld_global(D.tx32 + 2 * tl + e),
-                              (int32_t)((uint32_t)ld_global(D.perm + ld_global(D.tsrc + e)) * rs));
+                              (int32_t)((uint32_t)ld_global(D.perm + p) * rs));
+      pos[e - sg] = p;
+    }
   }
   wave_lds_sync();
   const int32_t cnt = ge - sg, padded = ((cnt + 2 * kStepSrc - 1) & ~(2 * kStepSrc - 1)) + 2 * kStepSrc;
-  if (lane < padded - cnt) ent[cnt + lane] = ent[0];
+  if (lane < padded - cnt) {
+    ent[cnt + lane] = ent[0];
+    pos[cnt + lane] = pos[0];
+  }
   wave_lds_sync();
 }
 
@@ -111,15 +119,31 @@ __device__ __forceinline__ void pin_step(StepSrc<TILES16>& s) {
   for (int q = 0; q < TILES16; ++q) asm volatile("" : "+v"(s.q[q]));
 }
 
-// One step: the lane's kernel value, then three products per column tile.
-// MASK: the pair may be at distance zero or past the list's end (valid false);
-// then the kernel value is zero.
+// The lane's target: its fixed-point coordinates, its sorted position t, and its
+// own entry's index within the current group (its self pair).
+struct StepTgt {
+  int32_t x, y, z, t, self_e;
+};
+
+// One step: the lane's kernel value, then three products per column tile.  The
+// lane's source is entry ei of the group (cnt real entries).  MASK: the pair may be
+// at distance zero, closer than kCloseQuanta quanta (then its difference comes
+// from the FP64 coordinates, as in the single-column sweep) or past the list's end
+// (then the kernel value is zero).
 template <int TILES16, bool HELM, bool MASK>
-__device__ __forceinline__ void mfma_step(const StepSrc<TILES16>& s, bool valid, int32_t tx, int32_t ty, int32_t tz,
-                                          float kturns, f4 (&p1)[TILES16], f4 (&p2)[TILES16],
-                                          f4 (&p3)[TILES16]) {
-  const F32::Geo g = F32::template geo<HELM, MASK>(tx, ty, tz, s.src.x, s.src.y, s.src.z, kturns);
-  const float w = (!MASK || valid) ? g.rinv : 0.0f;
+__device__ __forceinline__ void mfma_step(const StepSrc<TILES16>& s, int32_t ei, int32_t cnt, const StepTgt& tg,
+                                          const int32_t* pos, const ExactCtx& E, float kturns, f4 (&p1)[TILES16],
+                                          f4 (&p2)[TILES16], f4 (&p3)[TILES16]) {
+  F32::Geo g = F32::template geo<HELM, MASK>(tg.x, tg.y, tg.z, s.src.x, s.src.y, s.src.z, kturns);
+  bool valid = true;
+  if (MASK) {
+    valid = ei < cnt;
+    const bool close = valid && g.r2 < kCloseR2 && ei != tg.self_e;
+    if (__ballot(close)) {
+      if (close) g = exact_geo<HELM>(E, tg.t, pos[ei], kturns);
+    }
+  }
+  const float w = valid ? g.rinv : 0.0f;
   const float gr = g.c * w, gi = g.s * w;
   const float gs = gr + gi;
 #pragma unroll
@@ -140,21 +164,23 @@ struct MrhsState {
 
 // Two steps (8 entries from e0): the loads of each step are issued one step ahead.
 template <int TILES16, bool HELM, bool FAST, bool MASK>
-__device__ __forceinline__ void mrhs_block(MrhsState<TILES16>& S, const int4* ent, int32_t e0, int32_t cnt, int kk,
-                                           const float2* qb, int m, uint32_t lcol, const int32_t (&col)[TILES16],
-                                           int32_t tx, int32_t ty, int32_t tz, float kturns) {
+__device__ __forceinline__ void mrhs_block(MrhsState<TILES16>& S, const int4* ent, const int32_t* pos, int32_t e0,
+                                           int32_t cnt, int kk, const float2* qb, int m, uint32_t lcol,
+                                           const int32_t (&col)[TILES16], const StepTgt& tg, const ExactCtx& E,
+                                           float kturns) {
   S.b.src = ent[e0 + kStepSrc + kk];
   load_q<TILES16, FAST>(S.b, qb, m, lcol, col);
-  mfma_step<TILES16, HELM, MASK>(S.a, e0 + kk < cnt, tx, ty, tz, kturns, S.p1, S.p2, S.p3);
+  mfma_step<TILES16, HELM, MASK>(S.a, e0 + kk, cnt, tg, pos, E, kturns, S.p1, S.p2, S.p3);
   S.a.src = ent[e0 + 2 * kStepSrc + kk];
   load_q<TILES16, FAST>(S.a, qb, m, lcol, col);
-  mfma_step<TILES16, HELM, MASK>(S.b, e0 + kStepSrc + kk < cnt, tx, ty, tz, kturns, S.p1, S.p2, S.p3);
+  mfma_step<TILES16, HELM, MASK>(S.b, e0 + kStepSrc + kk, cnt, tg, pos, E, kturns, S.p1, S.p2, S.p3);
 }
 
 template <int TILES16, bool HELM, bool CSR, bool FAST>
 __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __restrict__ desc,
                                               const int4* __restrict__ items, XcdSplit split, int wpb) {
   __shared__ int4 lds_ent[kWavesPerBlock][kGroupSrc];
+  __shared__ int32_t lds_pos[kWavesPerBlock][kGroupSrc];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   if (wv >= wpb) return;
@@ -186,14 +212,17 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
     s1 = ld_uniform(D.tile_start + T + 1);
   }
   // entries [s0, s_self) are the box's own points (listed first); a zero distance
-  // can only occur there, unless points of distinct boxes may coincide
-  const int32_t s_self = D.may_coincide ? s1 : s0 + (bt1 - bt0);
+  // or a close pair can only occur there, unless points of distinct boxes may
+  // coincide or the box is marked near
+  const bool near_box = D.near != nullptr && ld_uniform(D.near + T) != 0;
+  const int32_t s_self = (D.may_coincide || near_box) ? s1 : s0 + (bt1 - bt0);
   const int64_t n = D.n;
   const int i = lane & 15;    // target row of A, column of B
   const int kk = lane >> 4;   // source of the step
   // rows past the tile's last target repeat its first; their sums are never stored
   const int32_t t = t_first + (i < nt ? i : 0);
-  const int32_t tx = ld_global(D.sx32 + t), ty = ld_global(D.sx32 + n + t), tz = ld_global(D.sx32 + 2 * n + t);
+  StepTgt tg{ld_global(D.sx32 + t), ld_global(D.sx32 + n + t), ld_global(D.sx32 + 2 * n + t), t, 0};
+  const ExactCtx E{D.sx64, n, D.qinv};
   const float kturns = D.kturns;
   const float2* qb = io.q[inst];
   const uint32_t lcol = 8u * (uint32_t)(rg + i);
@@ -213,9 +242,11 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
     S.p3[q] = f4{0.f, 0.f, 0.f, 0.f};
   }
   int4* ent = lds_ent[wv];
+  int32_t* pos = lds_pos[wv];
   for (int32_t sg = s0; sg < s1; sg += kGroupCap) {
     const int32_t cnt = min(s1 - sg, kGroupCap);
-    stage_group<CSR, FAST>(T, sg, sg + cnt, D, n, m, ent, lane);
+    stage_group<CSR, FAST>(T, sg, sg + cnt, D, n, m, ent, pos, lane);
+    tg.self_e = (t - bt0) + (s0 - sg);  // own points are listed first
     S.a.src = ent[kk];
     load_q<TILES16, FAST>(S.a, qb, m, lcol, col);
     pin_step<TILES16>(S.a);
@@ -225,10 +256,10 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
     const int32_t plain_from = max(0, s_self - sg);
     int32_t e0 = 0;
     for (; e0 < cnt && e0 < plain_from; e0 += 2 * kStepSrc)
-      mrhs_block<TILES16, HELM, FAST, true>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
+      mrhs_block<TILES16, HELM, FAST, true>(S, ent, pos, e0, cnt, kk, qb, m, lcol, col, tg, E, kturns);
     for (; e0 + 2 * kStepSrc <= cnt; e0 += 2 * kStepSrc)
-      mrhs_block<TILES16, HELM, FAST, false>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
-    if (e0 < cnt) mrhs_block<TILES16, HELM, FAST, true>(S, ent, e0, cnt, kk, qb, m, lcol, col, tx, ty, tz, kturns);
+      mrhs_block<TILES16, HELM, FAST, false>(S, ent, pos, e0, cnt, kk, qb, m, lcol, col, tg, E, kturns);
+    if (e0 < cnt) mrhs_block<TILES16, HELM, FAST, true>(S, ent, pos, e0, cnt, kk, qb, m, lcol, col, tg, E, kturns);
     wave_lds_sync();
   }
   // D[row][col]: lane j + 16 (row / 4), register row % 4
@@ -240,30 +271,6 @@ __global__ void __launch_bounds__(kBlock) k_mrhs(BatchIO io, const InstDesc* __r
       re[r][q] = S.p1[q][r] - S.p2[q][r];
       im[r][q] = S.p3[q][r] - S.p1[q][r] - S.p2[q][r];
     }
-  // close pairs of the tile's targets (FP32 plans, rare): exact minus computed
-  // kernel value times the source's strengths, added to the target's row
-  if (D.cp_num) {
-    const int32_t nc = ld_uniform(D.cp_num + T);
-    if (nc) {
-      const int32_t c0 = ld_uniform(D.cp_off + T);
-      for (int32_t e = c0; e < c0 + nc; ++e) {
-        const int32_t row = ld_uniform(D.cp_tgt + e) - t_first;
-        if (row < 0 || row >= nt || (row >> 2) != kk) continue;
-        const float2 dg = D.cp_g[e];
-        const float2* qr = qb + (int64_t)D.perm[D.cp_src[e]] * m;
-#pragma unroll
-        for (int q = 0; q < TILES16; ++q) {
-          const float2 v = qr[col[q]];
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (r == (row & 3)) {
-              re[r][q] += dg.x * v.x - dg.y * v.y;
-              im[r][q] += dg.x * v.y + dg.y * v.x;
-            }
-        }
-      }
-    }
-  }
   float2* y = io.y[inst];
   const float sc = D.scale;
 #pragma unroll
@@ -299,13 +306,9 @@ InstDesc make_desc(const p2p_plan_s* P) {
   d.kturns = (float)(P->k * std::ldexp(1.0, P->qexp) / (2.0 * M_PI));
   d.scale = (float)(std::ldexp(1.0, -P->qexp) / (4.0 * M_PI));
   d.may_coincide = P->may_coincide ? 1 : 0;
-  if (P->n_close > 0) {
-    d.cp_num = P->cp_num;
-    d.cp_off = P->cp_off;
-    d.cp_tgt = P->cp_tgt;
-    d.cp_src = P->cp_src;
-    d.cp_g = P->cp_g;
-  }
+  d.near = P->near;
+  d.sx64 = P->sx64;
+  d.qinv = std::ldexp(1.0, -P->qexp);
   return d;
 }
 

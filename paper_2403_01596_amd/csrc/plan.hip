@@ -409,9 +409,7 @@ struct DevStatus {
   uint64_t maxsep;     // bits of the largest per-axis near-pair difference (>= 0)
   uint64_t maxabs;     // bits of the largest |coordinate|
   uint64_t zero;       // zero-distance pairs (statistics only)
-  uint64_t ncp;        // close-pair entries (the entry offsets are carved from it)
-  uint32_t ncbox;      // boxes with close-pair entries (length of their list)
-  uint32_t fxc;        // distinct points of distinct boxes share their fixed-point coordinates
+  uint64_t ncp;        // FP32 plans: close pairs (statistics only)
 };
 
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1;
@@ -742,9 +740,11 @@ __device__ __forceinline__ int32_t fixed_point(double x, int qexp) {
 }
 
 // FILL false: neighbour counts, neighbourhood sizes and the geometry bounds.  FILL
-// true: the lists themselves and, when sx32 is given, the fixed-point coordinates
-// of the box's own points.  Each half of a wavefront takes one box (27 of its 32
-// lanes look up the neighbours), so a wavefront has two boxes' lookups in flight.
+// true: the lists themselves and, when sx32 is given (FP32 plans), the fixed-point
+// coordinates of the box's own points and the box's near flag: whether the
+// bounding box of another neighbour comes within reach of the box's own on every
+// axis.  Each half of a wavefront takes one box (27 of its 32 lanes look up the
+// neighbours), so a wavefront has two boxes' lookups in flight.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box_key,
                                              const int32_t* __restrict__ box_start, const double* __restrict__ bb,
@@ -752,7 +752,8 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
                                              int32_t* __restrict__ cnt, int32_t* __restrict__ src,
                                              const int32_t* __restrict__ nbr_start, int32_t* __restrict__ nbr_idx,
                                              Partial* __restrict__ part, const double* __restrict__ sx64,
-                                             int32_t* __restrict__ sx32, int64_t n, int qexp) {
+                                             int32_t* __restrict__ sx32, int64_t n, int qexp,
+                                             int32_t* __restrict__ near, double reach) {
   __shared__ uint64_t ldsl[kWavesPerBlockPlan];
   __shared__ double ldsd[kWavesPerBlockPlan];
   __shared__ uint32_t ldsu[kWavesPerBlockPlan];
@@ -782,10 +783,24 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
         rank += (Sj >= 0 && Sj < S) ? 1 : 0;
       }
       if (found) nbr_idx[nbr_start[T] + rank] = S;
-      if (sx32 && live) {
-        const int32_t p1 = box_start[T + 1];
-        for (int32_t p = box_start[T] + h; p < p1; p += 32)
-          for (int d = 0; d < 3; ++d) sx32[d * n + p] = fixed_point(sx64[d * n + p], qexp);
+      if (sx32) {
+        if (live) {
+          const int32_t p1 = box_start[T + 1];
+          for (int32_t p = box_start[T] + h; p < p1; p += 32)
+            for (int d = 0; d < 3; ++d) sx32[d * n + p] = fixed_point(sx64[d * n + p], qexp);
+        }
+        uint32_t close = 0;
+        if (found && S != T) {
+          bool within = true;
+          for (int a = 0; a < 3; ++a) {
+            const double gap = fmax(bb[6 * (int64_t)S + a] - bb[6 * (int64_t)T + 3 + a],
+                                    bb[6 * (int64_t)T + a] - bb[6 * (int64_t)S + 3 + a]);
+            within = within && gap < reach;
+          }
+          close = within ? 1u : 0u;
+        }
+        close = half_or(close);
+        if (h == 31 && live) near[T] = (int32_t)close;
       }
     } else {
       uint32_t ns = 0;
@@ -874,174 +889,6 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
   }
 }
 
-// ---------------------------------------------------------------------------
-// Close pairs of FP32 plans.  The FP32 kernels form a pair's difference from
-// fixed-point coordinates, exact as an integer, but each coordinate carries up to
-// half a quantum of rounding; for a pair only a few quanta apart that is a large
-// part of the distance.  Every near pair (i, j) with fixed-point difference D,
-// |D|^2 < kCloseQuanta^2, gets an entry holding the exact kernel values (FP64
-// coordinates, the difference x_i - x_j of the definition) minus the values the
-// kernels compute from the fixed-point coordinates (F32::geo, the same code), so
-// that adding entry times strength to the kernel's sum leaves the exact term.
-// Pairs at FP64 distance zero are skipped by the definition and get no entry.
-// ---------------------------------------------------------------------------
-struct CloseArgs {
-  const int32_t* box_start;
-  const int32_t* nbr_start;
-  const int32_t* nbr_idx;
-  const int32_t* sx32;   // [3][n] fixed-point coordinates
-  const double* sx64;    // [3][n] FP64 coordinates
-  const double* bb;      // per box: lo x, y, z, hi x, y, z (FP64)
-  int64_t n;
-  DevStatus* status;
-  double reach;          // (kCloseQuanta + 2) quanta: boxes whose bounding boxes are
-                         // farther apart on some axis hold no close pair between them
-  int32_t* num;          // [B] entries per box (count pass)
-  int32_t* off;          // [B] first entry of each box that has any (count pass)
-  int32_t* list;         // boxes that have entries (count pass)
-  // filling pass
-  int64_t cap;
-  int32_t* tgt;
-  int32_t* src;
-  float2* g;             // (c + i s) / r, exact minus computed, quantum units
-  float2* h;             // [3][cap] (c + i s)(i k - 1/r) d / r^2, exact minus computed
-  double k;
-  int qexp;
-  float kturns;          // k 2^qexp / (2 pi), as the FP32 sweep has it
-  float kw;              // k 2^qexp, as the FP32 reverse pass has it
-};
-
-// Entry e for target t and source s (sorted positions).
-__device__ void close_entry(const CloseArgs& A, int32_t t, int32_t s, int64_t e) {
-  const int64_t n = A.n;
-  // exact: the FP64 difference of the definition, scaled to quanta (a power of two)
-  double d[3];
-  for (int a = 0; a < 3; ++a) d[a] = ldexp(A.sx64[a * n + t] - A.sx64[a * n + s], -A.qexp);
-  const double rq = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  const double ri = 1.0 / rq;
-  const double kq = A.k * ldexp(1.0, A.qexp);  // radians per quantum
-  double c = 1.0, sn = 0.0;
-  if (A.k != 0.0) {
-    const double th = A.k * ldexp(rq, A.qexp);
-    c = cos(th);
-    sn = sin(th);
-  }
-  const double er = c * ri, ei = sn * ri;
-  const double hr = -(c * ri + sn * kq) * ri * ri, hi = (c * kq - sn * ri) * ri * ri;
-  // computed: the FP32 kernels' geometry and their products, in their order
-  const int32_t tx = A.sx32[t], ty = A.sx32[n + t], tz = A.sx32[2 * n + t];
-  const int32_t sx = A.sx32[s], sy = A.sx32[n + s], sz = A.sx32[2 * n + s];
-  const F32::Geo gm = A.k != 0.0 ? F32::geo<true, true>(tx, ty, tz, sx, sy, sz, A.kturns)
-                                 : F32::geo<false, true>(tx, ty, tz, sx, sy, sz, A.kturns);
-  const float gr = gm.c * gm.rinv, gi = gm.s * gm.rinv;
-  const float dr = -fmaf(gm.s, A.kw, gr), di = fmaf(gm.c, A.kw, -gi);
-  const float rr = gm.rinv * gm.rinv;
-  const float dm[3] = {gm.dx, gm.dy, gm.dz};
-  A.tgt[e] = t;
-  A.src[e] = s;
-  A.g[e] = make_float2((float)(er - (double)gr), (float)(ei - (double)gi));
-  for (int a = 0; a < 3; ++a) {
-    const double w = (double)rr * (double)dm[a];
-    A.h[a * A.cap + e] = make_float2((float)(hr * d[a] - (double)dr * w), (float)(hi * d[a] - (double)di * w));
-  }
-}
-
-// One wavefront per box (count pass: every box; filling pass: the boxes listed by
-// the count pass), lanes over its targets, the candidate sources walked one at a
-// time from scalar registers.  Candidates: the box's own points, and the points of
-// a neighbour box whose bounding box comes within reach of the box's on every
-// axis (rare: bounding boxes of adjacent boxes are usually further apart than
-// the reach).  A source passes the first test when each axis of D lies in
-// [-kCloseQuanta, kCloseQuanta): with u = t + kCloseQuanta, the three values u - s
-// are then all below 2 kCloseQuanta, a power of two, and so is their OR.
-constexpr int kCloseFillGrid = 512;  // workgroups of the filling pass (grid-stride over its list)
-
-template <bool FILL>
-__global__ void __launch_bounds__(kBlock) k_close(CloseArgs A) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t n = A.n;
-  const int32_t nw = FILL ? (int32_t)A.status->ncbox : A.status->nbox;
-  for (int32_t w = uniform((int32_t)(blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave)); w < nw;
-       w += gridDim.x * kWavesPerBlockPlan) {
-    const int32_t T = FILL ? ld_uniform(A.list + w) : w;
-    int64_t base = 0;
-    if (FILL) {
-      base = ld_uniform(A.off + T);
-      if (base + ld_uniform(A.num + T) > A.cap) continue;  // redone with room by the host
-    }
-    const int32_t t0 = ld_uniform(A.box_start + T), t1 = ld_uniform(A.box_start + T + 1);
-    const int32_t j0 = ld_uniform(A.nbr_start + T), j1 = ld_uniform(A.nbr_start + T + 1);
-    int32_t sl = -1;
-    bool cand = false;
-    if (lane < j1 - j0) {
-      sl = A.nbr_idx[j0 + lane];
-      cand = sl != T;
-      for (int a = 0; a < 3 && cand; ++a) {
-        const double gap = fmax(A.bb[6 * (int64_t)sl + a] - A.bb[6 * (int64_t)T + 3 + a],
-                                A.bb[6 * (int64_t)T + a] - A.bb[6 * (int64_t)sl + 3 + a]);
-        cand = gap < A.reach;
-      }
-    }
-    const uint64_t cmask = __ballot(cand);
-    uint32_t count = 0;
-    for (int32_t tb = t0; tb < t1; tb += kWave) {
-      const int32_t t = tb + lane;
-      const bool tv = t < t1;
-      const int32_t tx = tv ? A.sx32[t] : 0, ty = tv ? A.sx32[n + t] : 0, tz = tv ? A.sx32[2 * n + t] : 0;
-      const uint32_t ux = (uint32_t)tx + kCloseQuanta, uy = (uint32_t)ty + kCloseQuanta,
-                     uz = (uint32_t)tz + kCloseQuanta;
-      // the own box first, then each candidate neighbour
-      uint64_t rest = cmask;
-      for (int32_t S = T;;) {
-        const bool own = S == T;
-        const int32_t s0 = ld_uniform(A.box_start + S), s1 = ld_uniform(A.box_start + S + 1);
-        for (int32_t s = s0; s < s1; ++s) {
-          const int32_t sx = ld_uniform(A.sx32 + s), sy = ld_uniform(A.sx32 + n + s),
-                        sz = ld_uniform(A.sx32 + 2 * n + s);
-          const uint32_t any = (ux - (uint32_t)sx) | (uy - (uint32_t)sy) | (uz - (uint32_t)sz);
-          uint64_t hm = __ballot(tv && any < 2u * (uint32_t)kCloseQuanta);
-          if (own && s >= tb && s < tb + kWave) hm &= ~(1ull << (s - tb));  // the self pair
-          if (!hm) continue;
-          bool hit = false;
-          if ((hm >> lane) & 1ull) {
-            const int64_t dx = (int32_t)((uint32_t)tx - (uint32_t)sx), dy = (int32_t)((uint32_t)ty - (uint32_t)sy),
-                          dz = (int32_t)((uint32_t)tz - (uint32_t)sz);
-            hit = dx * dx + dy * dy + dz * dz < (int64_t)kCloseQuanta * kCloseQuanta;
-            if (hit) {
-              const bool same = A.sx64[t] == A.sx64[s] && A.sx64[n + t] == A.sx64[n + s] &&
-                                A.sx64[2 * n + t] == A.sx64[2 * n + s];
-              hit = !same;
-              // distinct points of distinct boxes on one fixed-point position: the
-              // kernels must mask every chunk, or their unmasked form divides by zero
-              if (!FILL && hit && !own && dx == 0 && dy == 0 && dz == 0) atomicOr(&A.status->fxc, 1u);
-            }
-          }
-          if (FILL) {
-            const uint64_t wm = __ballot(hit);
-            if (hit) close_entry(A, t, s, base + __popcll(wm & ((1ull << lane) - 1ull)));
-            base += __popcll(wm);
-          } else {
-            count += hit ? 1u : 0u;
-          }
-        }
-        if (!rest) break;
-        S = __builtin_amdgcn_readlane(sl, __builtin_ctzll(rest));
-        rest &= rest - 1;
-      }
-    }
-    if (!FILL) {
-      const uint32_t tot = wave_add63(count);
-      if (lane == kWave - 1) {
-        A.num[T] = (int32_t)tot;
-        if (tot) {
-          A.off[T] = (int32_t)atomicAdd((unsigned long long*)&A.status->ncp, (unsigned long long)tot);
-          A.list[atomicAdd(&A.status->ncbox, 1u)] = T;
-        }
-      }
-    }
-  }
-}
-
 // Processing order of the sweep: boxes in decreasing order of their pair slots,
 // bucketed on a log scale (8 buckets per octave), Morton order inside a bucket.
 __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict__ box_start,
@@ -1102,6 +949,56 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
   }
   const uint64_t zb = block_combine63((uint64_t)wave_add63(z), lds, [](uint64_t a, uint64_t b) { return a + b; });
   if (threadIdx.x == 0) part[blockIdx.x] = zb;
+}
+
+// Statistics of FP32 plans: ordered near pairs whose fixed-point difference is
+// shorter than kCloseQuanta quanta and whose FP64 distance is not zero -- the pairs
+// whose geometry the kernels take from the FP64 coordinates.  As k_count_zero: one
+// wavefront per box, targets and sources in registers; the neighbour boxes are
+// visited only for boxes marked near (no other box holds such a pair with them).
+__global__ void __launch_bounds__(kBlock) k_count_close(const int32_t* __restrict__ sx32,
+                                                     const double* __restrict__ sx, int64_t n,
+                                                     const int32_t* __restrict__ box_start,
+                                                     const int32_t* __restrict__ nbr_start,
+                                                     const int32_t* __restrict__ nbr_idx,
+                                                     const int32_t* __restrict__ near, int32_t nb,
+                                                     uint64_t* __restrict__ part) {
+  __shared__ uint64_t lds[kWavesPerBlockPlan];
+  const int64_t T = (int64_t)blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  constexpr uint64_t lim = (uint64_t)kCloseQuanta * (uint64_t)kCloseQuanta;
+  uint32_t c = 0;
+  if (T < nb) {
+    const bool all = near[T] != 0;
+    const int32_t e0 = all ? nbr_start[T] : 0, e1 = all ? nbr_start[T + 1] : 1;
+    const int32_t b0 = box_start[T], b1 = box_start[T + 1];
+    for (int32_t tb = b0; tb < b1; tb += kWave) {
+      const int nt = min(kWave, b1 - tb);
+      const int32_t ti = tb + min(lane, nt - 1);
+      const int32_t tx = sx32[ti], ty = sx32[n + ti], tz = sx32[2 * n + ti];
+      const double fx = sx[ti], fy = sx[n + ti], fz = sx[2 * n + ti];
+      for (int32_t e = e0; e < e1; ++e) {
+        const int32_t S = all ? nbr_idx[e] : (int32_t)T;
+        const int32_t s0 = box_start[S], s1 = box_start[S + 1];
+        for (int32_t sb = s0; sb < s1; sb += kWave) {
+          const bool sl = lane < s1 - sb;
+          const int32_t si = sl ? sb + lane : s0;
+          const int32_t qx = sx32[si], qy = sx32[n + si], qz = sx32[2 * n + si];
+          const double gx = sx[si], gy = sx[n + si], gz = sx[2 * n + si];
+          for (int j = 0; j < nt; ++j) {
+            const int64_t dx = (int32_t)((uint32_t)__builtin_amdgcn_readlane(tx, j) - (uint32_t)qx);
+            const int64_t dy = (int32_t)((uint32_t)__builtin_amdgcn_readlane(ty, j) - (uint32_t)qy);
+            const int64_t dz = (int32_t)((uint32_t)__builtin_amdgcn_readlane(tz, j) - (uint32_t)qz);
+            const uint64_t d2 = (uint64_t)(dx * dx) + (uint64_t)(dy * dy) + (uint64_t)(dz * dz);
+            const bool same = gx == lane_read(fx, j) && gy == lane_read(fy, j) && gz == lane_read(fz, j);
+            c += (sl && d2 < lim && !same) ? 1u : 0u;
+          }
+        }
+      }
+    }
+  }
+  const uint64_t cb = block_combine63((uint64_t)wave_add63(c), lds, [](uint64_t a, uint64_t b) { return a + b; });
+  if (threadIdx.x == 0) part[blockIdx.x] = cb;
 }
 
 // out = sum of a[0..n), one workgroup: per-thread sums, then a tree in LDS.
@@ -1420,7 +1317,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   //         The counting pass also zeroes entry B, so scanning B + 1 entries gives
   //         the offsets of the B boxes and, at index B, the totals.
   hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
-                     nullptr, nullptr, part, nullptr, nullptr, n, 0);
+                     nullptr, nullptr, part, nullptr, nullptr, n, 0, nullptr, 0.0);
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
   {  // both box-indexed arrays in one set of launches (partu is free once the sort is done)
@@ -1473,20 +1370,13 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     return fail(P2P_ERR_RANGE, "coordinates are too far from the origin for the FP32 fixed-point grid");
 
   // ---- 6. second allocation: neighbour lists, replicated source lists and, for
-  //         FP32 plans, the close-pair corrections (room for the usual count:
-  //         a few thousand entries per million points; more is handled below)
-  P->cp_cap = f64 ? 0 : std::max<int64_t>(16384, n / 32);
+  //         FP32 plans, the near flags
   auto carve2 = [&](Bump& b) {
     P->nbr_idx = b.take<int32_t>(P->nnz);
     P->tile_src = tiles ? b.take<int32_t>(P->tile_len) : nullptr;
     P->tile_x64 = (tiles && f64) ? b.take<double>(3 * P->tile_len) : nullptr;
     P->tile_x32 = (tiles && !f64) ? b.take<int32_t>(3 * P->tile_len) : nullptr;
-    P->cp_num = f64 ? nullptr : b.take<int32_t>(B);
-    P->cp_off = f64 ? nullptr : b.take<int32_t>(B);
-    P->cp_tgt = f64 ? nullptr : b.take<int32_t>(P->cp_cap);
-    P->cp_src = f64 ? nullptr : b.take<int32_t>(P->cp_cap);
-    P->cp_g = f64 ? nullptr : b.take<float2>(P->cp_cap);
-    P->cp_h = f64 ? nullptr : b.take<float2>(3 * P->cp_cap);
+    P->near = f64 ? nullptr : b.take<int32_t>(B);
   };
   const size_t bytes2 = measure(carve2);
   rc = dev_alloc(&P->arena2, bytes2);
@@ -1496,9 +1386,14 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     Bump b{(char*)P->arena2, 0};
     carve2(b);
   }
+  // two boxes whose bounding boxes are at least kCloseQuanta + 2 quanta apart on
+  // some axis hold no pair closer than kCloseQuanta quanta in fixed point (each
+  // coordinate rounds by at most half a quantum; the bounding boxes' FP64
+  // differences by far less than the second quantum of margin)
+  const double reach = std::ldexp((double)kCloseQuanta + 2.0, P->qexp);
   hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
                      dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
-                     P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp);
+                     P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp, P->near, reach);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)
@@ -1508,56 +1403,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
       hipLaunchKernelGGL(k_tile_fill<false>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
   }
-  // ---- 7. close-pair corrections (FP32): count pass over every box, then the
-  //         filling pass over the boxes that have entries
-  CloseArgs ca{};
-  if (!f64) {
-    const double quantum = std::ldexp(1.0, P->qexp);
-    ca = CloseArgs{P->box_start, P->nbr_start, P->nbr_idx, P->sx32, P->sx64, bb, n, status,
-                   (kCloseQuanta + 2) * quantum, P->cp_num, P->cp_off, v1, P->cp_cap, P->cp_tgt, P->cp_src,
-                   P->cp_g, P->cp_h, P->k, P->qexp,
-                   (float)(P->k * quantum / (2.0 * M_PI)), (float)(P->k * quantum)};
-    hipLaunchKernelGGL(k_close<false>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
-                       dim3(kBlock), 0, s, ca);
-    hipLaunchKernelGGL(k_close<true>, dim3(kCloseFillGrid), dim3(kBlock), 0, s, ca);
-  }
   P2P_HIP(hipGetLastError());
-  {  // last readback: the close-pair count; it also waits for all of the build
-    StatusCopy copy;
-    rc = copy.start(status, s);
-    if (rc != P2P_OK) return rc;
-    rc = copy.finish(&hs);
-    if (rc != P2P_OK) return rc;
-  }
-  if (!f64) {
-    P->n_close = (int64_t)hs.ncp;
-    if (hs.fxc) P->may_coincide = true;
-    if (P->n_close > P->cp_cap) {  // more entries than the room reserved: their own block
-      if (P->n_close > 0x7fffffffll) return fail(P2P_ERR_RANGE, "more than 2^31 close pairs");
-      const int64_t cap = P->n_close;
-      auto carve3 = [&](Bump& b) {
-        P->cp_tgt = b.take<int32_t>(cap);
-        P->cp_src = b.take<int32_t>(cap);
-        P->cp_g = b.take<float2>(cap);
-        P->cp_h = b.take<float2>(3 * cap);
-      };
-      const size_t bytes3 = measure(carve3);
-      rc = dev_alloc(&P->arena3, bytes3);
-      if (rc != P2P_OK) return rc;
-      P->device_bytes += bytes3;
-      Bump b{(char*)P->arena3, 0};
-      carve3(b);
-      P->cp_cap = cap;
-      ca.cap = cap;
-      ca.tgt = P->cp_tgt;
-      ca.src = P->cp_src;
-      ca.g = P->cp_g;
-      ca.h = P->cp_h;
-      hipLaunchKernelGGL(k_close<true>, dim3(kCloseFillGrid), dim3(kBlock), 0, s, ca);
-      P2P_HIP(hipGetLastError());
-      P2P_HIP(hipStreamSynchronize(s));
-    }
-  }
   return P2P_OK;
 }
 
@@ -1575,6 +1421,11 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
     hipLaunchKernelGGL(k_count_zero, dim3(g), dim3(kBlock), 0, s, P->sx64, P->n, P->box_start, P->nbr_start,
                        P->nbr_idx, (int32_t)P->B, !P->may_coincide, part);
     hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->zero);
+    if (P->near) {
+      hipLaunchKernelGGL(k_count_close, dim3(g), dim3(kBlock), 0, s, P->sx32, P->sx64, P->n, P->box_start,
+                         P->nbr_start, P->nbr_idx, P->near, (int32_t)P->B, part);
+      hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->ncp);
+    }
   }
   P2P_HIP(hipGetLastError());
   DevStatus hs;
@@ -1582,6 +1433,7 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   if (rc != P2P_OK) return rc;
   P->n_zero = (int64_t)hs.zero;
   P->n_pairs = P->n_slots - P->n_zero;
+  P->n_close = (int64_t)hs.ncp;
   return P2P_OK;
 }
 

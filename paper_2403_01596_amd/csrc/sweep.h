@@ -40,21 +40,31 @@ struct F32 {
   using cplx = float2;
   static constexpr int K = 8, K1 = 8;  // chunks of 64 sources per group (K1: one column)
   struct Geo {
-    float dx, dy, dz, rinv, c, s;
+    float dx, dy, dz, r2, rinv, c, s;
   };
   // k_turns: k * 2^qexp / (2 pi), the phase in turns per quantum of distance.
   // MASK: the pair may be at distance zero (then rinv = 0 and the term vanishes).
   template <bool HELM, bool MASK>
   __device__ static __forceinline__ Geo geo(int32_t tx, int32_t ty, int32_t tz, int32_t sx, int32_t sy, int32_t sz,
-                                            float k_turns) {
-    Geo g;
+                                            float k_turns, float floor_r2 = 0.0f) {
     // x_target - x_source: exact modulo 2^32, exact as an integer for near pairs
-    g.dx = (float)(int32_t)((uint32_t)tx - (uint32_t)sx);
-    g.dy = (float)(int32_t)((uint32_t)ty - (uint32_t)sy);
-    g.dz = (float)(int32_t)((uint32_t)tz - (uint32_t)sz);
+    return from_d<HELM, MASK>((float)(int32_t)((uint32_t)tx - (uint32_t)sx),
+                              (float)(int32_t)((uint32_t)ty - (uint32_t)sy),
+                              (float)(int32_t)((uint32_t)tz - (uint32_t)sz), k_turns, floor_r2);
+  }
+  // The same from a difference already in FP32 (quantum units).  MASK with a
+  // positive floor: every pair with r2 below it gets rinv = 0 (the sweep adds
+  // those terms separately).
+  template <bool HELM, bool MASK>
+  __device__ static __forceinline__ Geo from_d(float dx, float dy, float dz, float k_turns, float floor_r2 = 0.0f) {
+    Geo g;
+    g.dx = dx;
+    g.dy = dy;
+    g.dz = dz;
     const float r2 = __builtin_fmaf(g.dz, g.dz, __builtin_fmaf(g.dy, g.dy, g.dx * g.dx));
     const float ri = __builtin_amdgcn_rsqf(r2);
-    g.rinv = MASK ? ((r2 > 0.0f) ? ri : 0.0f) : ri;
+    g.r2 = r2;
+    g.rinv = MASK ? ((r2 > floor_r2) ? ri : 0.0f) : ri;
     if (HELM) {
       const float turns = (r2 * g.rinv) * k_turns;
       g.c = __builtin_amdgcn_cosf(turns);
@@ -155,6 +165,35 @@ struct F64 {
   }
 };
 
+// FP32 plans: a pair whose fixed-point difference is shorter than kCloseQuanta
+// quanta (r2 below kCloseR2 in quantum units) takes its coordinate difference from
+// the FP64 coordinates instead -- the difference of the definition, exact for such
+// a pair, rounded once to FP32 -- and the rest of its geometry as any other pair.
+// The rounding of fixed-point coordinates (half a quantum per axis) would move
+// its term by up to a quantum over its distance; for every other pair, at least
+// 2^20 quanta apart, by at most 2^-20 relative.  A pair at FP64 distance zero
+// gets rinv = 0, as the definition skips it.
+constexpr float kCloseR2 = (float)kCloseQuanta * (float)kCloseQuanta;
+
+struct ExactCtx {
+  const double* x;  // [3][n] FP64 coordinates, sorted order
+  int64_t n;
+  double qinv;      // 2^-qexp: length to quanta
+};
+
+template <bool HELM>
+__device__ __forceinline__ F32::Geo exact_geo(const ExactCtx& E, int32_t t, int32_t p, float k_turns) {
+  float d[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a] = (float)((E.x[a * E.n + t] - E.x[a * E.n + p]) * E.qinv);
+    // one axis at a time: this runs beside the sweep's live registers, and only
+    // one pair of FP64 temporaries fits there
+    asm volatile("" : "+v"(d[a])::"memory");
+  }
+  return F32::from_d<HELM, true>(d[0], d[1], d[2], k_turns);
+}
+
 // The paper's two-dimensional potential, G(r) = -ln(r) / (2 pi) = -ln(r^2) / (4 pi),
 // in FP64 on points of a plane (z equal for all points, so dz = 0).  geo() leaves
 // ln(r^2) in l (zero for a masked pair at distance zero); the operation scales.
@@ -199,16 +238,12 @@ struct SweepGeom {
   typename Tr::real kparam;      // F32: turns per quantum; F64: turns per unit length
   typename Tr::coord far;        // x offset of padding entries: farther than any near pair
   bool may_coincide;             // points of distinct boxes may coincide: mask every chunk
-  // F32 plans with close pairs (else cp_num is null): per box, entries
-  // [cp_off[T], cp_off[T] + cp_num[T]) of target, source, and the exact minus the
-  // computed kernel values (cp_h: [3][cp_cap])
-  const int32_t* cp_num;
-  const int32_t* cp_off;
-  const int32_t* cp_tgt;
-  const int32_t* cp_src;
-  const float2* cp_g;
-  const float2* cp_h;
-  int64_t cp_cap;
+  // FP32 plans: per box, nonzero if a neighbour box's bounding box comes within
+  // kCloseQuanta + 2 quanta of the box's own on every axis (only then can a pair
+  // of distinct boxes be close; see exact_geo); and the FP64 coordinates for those
+  // pairs
+  const int32_t* near;
+  ExactCtx exact;
 };
 
 template <class Tr>
@@ -225,14 +260,8 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
   G.n = P->n;
   G.perm = P->perm;
   G.may_coincide = P->may_coincide;
-  const bool close = std::is_same<Tr, F32>::value && P->n_close > 0;
-  G.cp_num = close ? P->cp_num : nullptr;
-  G.cp_off = P->cp_off;
-  G.cp_tgt = P->cp_tgt;
-  G.cp_src = P->cp_src;
-  G.cp_g = P->cp_g;
-  G.cp_h = P->cp_h;
-  G.cp_cap = P->cp_cap;
+  G.near = std::is_same<Tr, F32>::value ? P->near : nullptr;
+  G.exact = ExactCtx{P->sx64, P->n, std::ldexp(1.0, -P->qexp)};
   if constexpr (std::is_same<Tr, F32>::value) {
     G.tx = P->tile_x32;
     G.sx = P->sx32;
@@ -279,6 +308,8 @@ template <class Tr, class Op, bool CSR>
 struct SweepLds {
   typename Tr::real sums[Op::NA][kWave];
   int32_t idx[CSR ? kWave * Op::K : 1];
+  // FP32: the current target's close sources, as entries of the group (0 = sg)
+  int32_t close[std::is_same<Tr, F32>::value ? kWave * Op::K : 1];
 };
 
 // Which chunks of a group take the zero-distance mask: every chunk, the first
@@ -289,13 +320,16 @@ struct SweepLds {
 enum SweepMask { kMaskAll, kMaskFirst, kMaskNone };
 
 // All targets of the block [tb, te) against the group's chunks in registers.
-template <class Tr, class Op, bool HELM, int MODE, class LdsT>
+// The group holds entries [sg, s1) of the box's neighbourhood list; a target's
+// own entry (its self pair) is entry t + self_off of that list.
+template <class Tr, class Op, bool HELM, bool CSR, int MODE, class LdsT>
 __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& op, LdsT& L,
                                               const typename Tr::coord (&X)[Op::K],
                                               const typename Tr::coord (&Y)[Op::K],
                                               const typename Tr::coord (&Z)[Op::K],
                                               const typename Tr::real (&P)[Op::K][Op::NP > 0 ? Op::NP : 1], int nch,
-                                              int32_t tb, int32_t te, bool first_group) {
+                                              int32_t tb, int32_t te, bool first_group, int32_t sg, int32_t s1,
+                                              int32_t self_off) {
   using real = typename Tr::real;
   using coord = typename Tr::coord;
   constexpr int K = Op::K;
@@ -316,19 +350,59 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
     real acc[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) acc[a] = real(0);
+    int32_t nq = 0;  // queued close sources of target t
 #pragma unroll
     for (int c = 0; c < K; ++c)
       if (c < nch) {
         // c is a constant in each unrolled copy, so this choice costs no branch
         const bool masked = MODE == kMaskAll || (MODE == kMaskFirst && c == 0);
         if (masked) {
-          const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
-          op.template pair<HELM>(g, P[c], tp, acc);
+          if constexpr (std::is_same<Tr, F32>::value) {
+            // Pairs under kCloseQuanta quanta get no term here (rinv = 0); their
+            // sources, the self pair and padding entries excepted, are queued and
+            // taken from the FP64 coordinates below (rare).
+            const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam, kCloseR2);
+            uint64_t cm = __ballot(g.r2 < kCloseR2);
+            const int32_t sl = t + self_off - sg - c * kWave;
+            if (sl >= 0 && sl < kWave) cm &= ~(1ull << sl);
+            const int32_t nv = s1 - sg - c * kWave;
+            if (nv < kWave) cm &= nv > 0 ? (1ull << nv) - 1ull : 0ull;
+            if (cm) {
+              if ((cm >> lane) & 1ull) L.close[nq + __popcll(cm & ((1ull << lane) - 1ull))] = c * kWave + lane;
+              nq += __popcll(cm);
+            }
+            op.template pair<HELM>(g, P[c], tp, acc);
+          } else {
+            const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
+            op.template pair<HELM>(g, P[c], tp, acc);
+          }
         } else {
           const typename Tr::Geo g = Tr::template geo<HELM, false>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
           op.template pair<HELM>(g, P[c], tp, acc);
         }
       }
+    if constexpr (std::is_same<Tr, F32>::value) {
+      // the queued close pairs of target t, one per lane: the difference from the
+      // FP64 coordinates, then the same pair arithmetic
+      if (nq) {
+        wave_lds_sync();
+        // uniform trips; lanes past the queue's end repeat its first entry with
+        // a zero kernel value
+        for (int32_t j0 = 0; j0 < nq; j0 += kWave) {
+          const bool on = j0 + lane < nq;
+          const int32_t off = L.close[on ? j0 + lane : 0];
+          int32_t p;
+          if constexpr (CSR) p = L.idx[off];
+          else p = G.tsrc[sg + off];
+          real sp[Op::NP > 0 ? Op::NP : 1];
+          op.load_src(p, sp);
+          typename Tr::Geo g = exact_geo<HELM>(G.exact, t, p, G.kparam);
+          g.rinv = on ? g.rinv : 0.0f;
+          op.template pair<HELM>(g, sp, tp, acc);
+        }
+        wave_lds_sync();
+      }
+    }
     // accumulators in pairs: the even one's sum lands in lane 31, the odd one's
     // (and a last unpaired one's) in lane 63
 #pragma unroll
@@ -351,7 +425,6 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
 //   load_src(p, pay)      payload of the source at sorted position p
 //   load_tgt(t, pay)      payload of the target at sorted position t (uniform)
 //   pair<HELM>(geo, spay, tpay, acc)
-//   correct(G, e, t, acc) F32: add close-pair entry e of target t to its sums
 //   store(t, acc)         final values of target t (sorted position), by its lane
 template <class Tr, class Op, bool HELM, bool CSR>
 __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, SweepLds<Tr, Op, CSR>& L) {
@@ -376,6 +449,7 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
     s1 = ld_uniform(G.tile_start + T + 1);
   }
   const int64_t n = G.n, tl = G.tl;
+  const bool near_box = G.near != nullptr && ld_uniform(G.near + T) != 0;
   for (int32_t tb = t0; tb < t1; tb += kWave) {
     const int32_t te = min(tb + kWave, t1);
     for (int32_t sg = s0; sg < s1; sg += kWave * K) {
@@ -417,34 +491,25 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
         }
       }
       const bool first_group = sg == s0;
-      // A zero distance can only occur among the box's own points, entries
-      // [s0, s0 + n_T), unless points of distinct boxes may coincide.  Padding
-      // entries sit far away.  The first-chunk form needs all own points in the
-      // first chunk of the first group.
+      // A zero distance, or (FP32) a close pair, can only occur among the box's
+      // own points, entries [s0, s0 + n_T), unless points of distinct boxes may
+      // coincide or (FP32) the box is marked near.  Padding entries sit far away.
+      // The first-chunk form needs all own points in the first chunk of the first
+      // group.
       const bool own_here = sg < s0 + (t1 - t0);
-      if (G.may_coincide || (own_here && !(first_group && t1 - t0 <= kWave)))
-        sweep_targets<Tr, Op, HELM, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
+      const int32_t so = s0 - t0;
+      if (G.may_coincide || near_box || (own_here && !(first_group && t1 - t0 <= kWave)))
+        sweep_targets<Tr, Op, HELM, CSR, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
       else if (first_group)
-        sweep_targets<Tr, Op, HELM, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
+        sweep_targets<Tr, Op, HELM, CSR, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
       else
-        sweep_targets<Tr, Op, HELM, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group);
+        sweep_targets<Tr, Op, HELM, CSR, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
     }
     wave_lds_sync();
     real mine[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) mine[a] = L.sums[a][lane];
-    if constexpr (std::is_same<Tr, F32>::value) {
-      // close pairs of the box's targets: exact minus computed terms (rare)
-      if (G.cp_num) {
-        const int32_t nc = ld_uniform(G.cp_num + T);
-        if (nc) {
-          const int32_t c0 = ld_uniform(G.cp_off + T);
-          for (int32_t e = c0; e < c0 + nc; ++e)
-            if (ld_uniform(G.cp_tgt + e) == tb + lane) op.correct(G, e, tb + lane, mine);
-        }
-      }
-    }
     if (tb + lane < te) op.store(tb + lane, mine);
     wave_lds_sync();  // the sums are rewritten by the next block of targets
   }
