@@ -151,8 +151,7 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   *out = nullptr;
   if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
   if (n > 0 && (!xyz || (!box_ijk && !gspec))) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
-  // neighbour-list entries (at most 27 n) are 32-bit offsets
-  if (n > (int64_t)(0x7fffffff / 27)) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
+  if (n > kMaxPoints) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
   if (!std::isfinite(k) || k < 0) return fail(P2P_ERR_RANGE, "k must be finite and >= 0");
   p2p_opts o{P2P_C64, P2P_LAYOUT_TILES, 1, 0u, nullptr};
   if (opts) o = *opts;

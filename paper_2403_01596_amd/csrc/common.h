@@ -16,6 +16,8 @@ namespace p2p {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kIdBits = 21;      // box ids per axis live in [0, 2^21)
 constexpr int kBlock = 256;      // threads per workgroup for the streaming kernels
+// largest point count: neighbour-list entries (at most 27 n) are 32-bit offsets
+constexpr int64_t kMaxPoints = 0x7fffffff / 27;
 // FP32 plans: near pairs whose fixed-point difference is shorter than this many
 // quanta get their kernel value from the FP64 coordinates (see p2p_plan_s).
 // Every other pair is at least 2^20 quanta apart, so the rounding of its

@@ -52,9 +52,9 @@ struct F32 {
                               (float)(int32_t)((uint32_t)ty - (uint32_t)sy),
                               (float)(int32_t)((uint32_t)tz - (uint32_t)sz), k_turns, floor_r2);
   }
-  // The same from a difference already in FP32 (quantum units).  MASK with a
-  // positive floor: every pair with r2 below it gets rinv = 0 (the sweep adds
-  // those terms separately).
+  // The same from a difference already in FP32 (quantum units).  MASK: pairs with
+  // r2 <= floor_r2 get rinv = 0 (with the default floor, the pairs at distance
+  // zero; with a positive one, the sweep adds those terms separately).
   template <bool HELM, bool MASK>
   __device__ static __forceinline__ Geo from_d(float dx, float dy, float dz, float k_turns, float floor_r2 = 0.0f) {
     Geo g;
@@ -319,9 +319,46 @@ struct SweepLds {
 // accumulators at every join.
 enum SweepMask { kMaskAll, kMaskFirst, kMaskNone };
 
-// All targets of the block [tb, te) against the group's chunks in registers.
-// The group holds entries [sg, s1) of the box's neighbourhood list; a target's
-// own entry (its self pair) is entry t + self_off of that list.
+// Entries of the close-pair queue: the target (offset from the block's first)
+// and the source (entry of the group) of one close pair.
+__device__ __forceinline__ int32_t close_entry(int32_t t_off, int32_t e_off) { return (t_off << 16) | e_off; }
+constexpr int32_t kNoMiss = 0x7fffffff;
+
+// The close pairs of target t in chunk c of a group: lanes whose fixed-point r2 is
+// at most kCloseR2 (so that the FP32 geometry gave them no term; far: the others),
+// except the self pair and entries past the group's end.
+__device__ __forceinline__ uint64_t close_mask(uint64_t far, int32_t t, int32_t self_off, int32_t sg, int32_t s1,
+                                               int c) {
+  uint64_t cm = ~far;
+  const int32_t sl = t + self_off - sg - c * kWave;
+  if (sl >= 0 && sl < kWave) cm &= ~(1ull << sl);
+  const int32_t nv = s1 - sg - c * kWave;
+  if (nv < kWave) cm &= nv > 0 ? (1ull << nv) - 1ull : 0ull;
+  return cm;
+}
+
+// Appends the lanes of cm to the close-pair queue for target t, unless the queue
+// is stopped or cannot take them; then it is stopped and target t's entries are
+// dropped, to be found again by close_rescan from t_miss on.
+template <class LdsT>
+__device__ __forceinline__ void close_push(LdsT& L, uint64_t cm, int32_t t_off, int c, int32_t cap, int32_t nq_t,
+                                           int32_t t, int32_t& nq, int32_t& t_miss) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t k = __popcll(cm);
+  if (t_miss == kNoMiss && nq + k <= cap) {
+    if ((cm >> lane) & 1ull) L.close[nq + __popcll(cm & ((1ull << lane) - 1ull))] = close_entry(t_off, c * kWave + lane);
+    nq += k;
+  } else if (t_miss == kNoMiss) {
+    nq = nq_t;
+    t_miss = t;
+  }
+}
+
+// Targets [tb, te) against the group's chunks in registers.  The group holds
+// entries [sg, s1) of the box's neighbourhood list; a target's own entry (its
+// self pair) is entry t + self_off of that list.  FP32: the close pairs met are
+// queued in L.close (nq entries); t_miss is the first target whose pairs did not
+// fit, or kNoMiss.
 template <class Tr, class Op, bool HELM, bool CSR, int MODE, class LdsT>
 __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& op, LdsT& L,
                                               const typename Tr::coord (&X)[Op::K],
@@ -329,11 +366,12 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
                                               const typename Tr::coord (&Z)[Op::K],
                                               const typename Tr::real (&P)[Op::K][Op::NP > 0 ? Op::NP : 1], int nch,
                                               int32_t tb, int32_t te, bool first_group, int32_t sg, int32_t s1,
-                                              int32_t self_off) {
+                                              int32_t self_off, int32_t& nq, int32_t& t_miss) {
   using real = typename Tr::real;
   using coord = typename Tr::coord;
   constexpr int K = Op::K;
   constexpr int NT = Op::NT, NA = Op::NA;
+  constexpr int32_t kCap = kWave * K;  // one target's pairs of a group always fit
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t n = G.n;
   // target coordinates are fetched one target ahead
@@ -350,7 +388,7 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
     real acc[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) acc[a] = real(0);
-    int32_t nq = 0;  // queued close sources of target t
+    const int32_t nq_t = nq;  // the queue before target t
 #pragma unroll
     for (int c = 0; c < K; ++c)
       if (c < nch) {
@@ -358,19 +396,12 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
         const bool masked = MODE == kMaskAll || (MODE == kMaskFirst && c == 0);
         if (masked) {
           if constexpr (std::is_same<Tr, F32>::value) {
-            // Pairs under kCloseQuanta quanta get no term here (rinv = 0); their
-            // sources, the self pair and padding entries excepted, are queued and
-            // taken from the FP64 coordinates below (rare).
+            // Pairs under kCloseQuanta quanta get no term here (rinv = 0); the
+            // close ones among them (the self pair and padding entries are not)
+            // are queued and taken from the FP64 coordinates after the group.
             const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam, kCloseR2);
-            uint64_t cm = __ballot(g.r2 < kCloseR2);
-            const int32_t sl = t + self_off - sg - c * kWave;
-            if (sl >= 0 && sl < kWave) cm &= ~(1ull << sl);
-            const int32_t nv = s1 - sg - c * kWave;
-            if (nv < kWave) cm &= nv > 0 ? (1ull << nv) - 1ull : 0ull;
-            if (cm) {
-              if ((cm >> lane) & 1ull) L.close[nq + __popcll(cm & ((1ull << lane) - 1ull))] = c * kWave + lane;
-              nq += __popcll(cm);
-            }
+            const uint64_t cm = close_mask(__ballot(g.r2 > kCloseR2), t, self_off, sg, s1, c);
+            if (cm) close_push(L, cm, t - tb, c, kCap, nq_t, t, nq, t_miss);
             op.template pair<HELM>(g, P[c], tp, acc);
           } else {
             const typename Tr::Geo g = Tr::template geo<HELM, true>(px, py, pz, X[c], Y[c], Z[c], G.kparam);
@@ -381,28 +412,6 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
           op.template pair<HELM>(g, P[c], tp, acc);
         }
       }
-    if constexpr (std::is_same<Tr, F32>::value) {
-      // the queued close pairs of target t, one per lane: the difference from the
-      // FP64 coordinates, then the same pair arithmetic
-      if (nq) {
-        wave_lds_sync();
-        // uniform trips; lanes past the queue's end repeat its first entry with
-        // a zero kernel value
-        for (int32_t j0 = 0; j0 < nq; j0 += kWave) {
-          const bool on = j0 + lane < nq;
-          const int32_t off = L.close[on ? j0 + lane : 0];
-          int32_t p;
-          if constexpr (CSR) p = L.idx[off];
-          else p = G.tsrc[sg + off];
-          real sp[Op::NP > 0 ? Op::NP : 1];
-          op.load_src(p, sp);
-          typename Tr::Geo g = exact_geo<HELM>(G.exact, t, p, G.kparam);
-          g.rinv = on ? g.rinv : 0.0f;
-          op.template pair<HELM>(g, sp, tp, acc);
-        }
-        wave_lds_sync();
-      }
-    }
     // accumulators in pairs: the even one's sum lands in lane 31, the odd one's
     // (and a last unpaired one's) in lane 63
 #pragma unroll
@@ -416,6 +425,63 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
           L.sums[a][t - tb] = first_group ? acc[a] : L.sums[a][t - tb] + acc[a];
       }
     }
+  }
+}
+
+// FP32, after the queue filled up: the close pairs of targets [tf, te) found
+// again, with the sweep's own test on the group's coordinates (chunks in the
+// masked form only), into the emptied queue.  Returns the first target whose pairs
+// did not fit, or kNoMiss; the first target always fits.
+template <class Op, bool CSR, int MODE, class LdsT>
+__device__ __forceinline__ int32_t close_rescan(const SweepGeom<F32>& G, LdsT& L, const int32_t (&X)[Op::K],
+                                                const int32_t (&Y)[Op::K], const int32_t (&Z)[Op::K], int nch,
+                                                int32_t tb, int32_t tf, int32_t te, int32_t sg, int32_t s1,
+                                                int32_t self_off, int32_t& nq) {
+  constexpr int K = Op::K;
+  constexpr int32_t kCap = kWave * K;
+  const int64_t n = G.n;
+  int32_t t_miss = kNoMiss;
+  for (int32_t t = tf; t < te && t_miss == kNoMiss; ++t) {
+    const int32_t px = ld_uniform(G.sx + t), py = ld_uniform(G.sx + n + t), pz = ld_uniform(G.sx + 2 * n + t);
+    const int32_t nq_t = nq;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (c < nch && (MODE == kMaskAll || (MODE == kMaskFirst && c == 0))) {
+        const F32::Geo g = F32::template geo<false, false>(px, py, pz, X[c], Y[c], Z[c], 0.0f);
+        const uint64_t cm = close_mask(__ballot(g.r2 > kCloseR2), t, self_off, sg, s1, c);
+        if (cm) close_push(L, cm, t - tb, c, kCap, nq_t, t, nq, t_miss);
+      }
+  }
+  return t_miss;
+}
+
+// FP32: the queued close pairs of a group, one at a time (wave-uniform): the
+// difference from the FP64 coordinates, the pair arithmetic, and the term added
+// to its target's sums, which the group has already written.
+template <class Tr, class Op, bool HELM, bool CSR, class LdsT>
+__device__ __forceinline__ void close_terms(const SweepGeom<Tr>& G, const Op& op, LdsT& L, int32_t tb, int32_t sg,
+                                            int32_t nq) {
+  using real = typename Tr::real;
+  constexpr int NT = Op::NT, NP = Op::NP, NA = Op::NA;
+  const int lane = threadIdx.x & (kWave - 1);
+  wave_lds_sync();
+  for (int32_t j = 0; j < nq; ++j) {
+    const int32_t ent = uniform(L.close[j]);
+    const int32_t t = tb + (ent >> 16), off = ent & 0xffff;
+    int32_t p;
+    if constexpr (CSR) p = uniform(L.idx[off]);
+    else p = ld_uniform(G.tsrc + sg + off);
+    real tp[NT > 0 ? NT : 1], sp[NP > 0 ? NP : 1], a[NA];
+    op.load_tgt(t, tp);
+    op.load_src(p, sp);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a[i] = real(0);
+    op.template pair<HELM>(exact_geo<HELM>(G.exact, t, p, G.kparam), sp, tp, a);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) L.sums[i][t - tb] += a[i];
+    }
+    wave_lds_sync();
   }
 }
 
@@ -455,6 +521,17 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
     for (int32_t sg = s0; sg < s1; sg += kWave * K) {
       const int nch = min(K, (s1 - sg + kWave - 1) / kWave);
       if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, L.idx, lane);
+      const bool first_group = sg == s0;
+      // A zero distance, or (FP32) a close pair, can only occur among the box's
+      // own points, entries [s0, s0 + n_T), unless points of distinct boxes may
+      // coincide or (FP32) the box is marked near.  Padding entries sit far away.
+      // The first-chunk form needs all own points in the first chunk of the first
+      // group.
+      const bool own_here = sg < s0 + (t1 - t0);
+      const int32_t so = s0 - t0;
+      const int mode = (G.may_coincide || near_box || (own_here && !(first_group && t1 - t0 <= kWave)))
+                           ? kMaskAll
+                           : (first_group ? kMaskFirst : kMaskNone);
       coord X[K], Y[K], Z[K];
       real P[K][NP > 0 ? NP : 1];
 #pragma unroll
@@ -490,20 +567,30 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
           }
         }
       }
-      const bool first_group = sg == s0;
-      // A zero distance, or (FP32) a close pair, can only occur among the box's
-      // own points, entries [s0, s0 + n_T), unless points of distinct boxes may
-      // coincide or (FP32) the box is marked near.  Padding entries sit far away.
-      // The first-chunk form needs all own points in the first chunk of the first
-      // group.
-      const bool own_here = sg < s0 + (t1 - t0);
-      const int32_t so = s0 - t0;
-      if (G.may_coincide || near_box || (own_here && !(first_group && t1 - t0 <= kWave)))
-        sweep_targets<Tr, Op, HELM, CSR, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
-      else if (first_group)
-        sweep_targets<Tr, Op, HELM, CSR, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
+      int32_t nq = 0, t_miss = kNoMiss;
+      if (mode == kMaskAll)
+        sweep_targets<Tr, Op, HELM, CSR, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
+                                                   t_miss);
+      else if (mode == kMaskFirst)
+        sweep_targets<Tr, Op, HELM, CSR, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
+                                                     t_miss);
       else
-        sweep_targets<Tr, Op, HELM, CSR, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so);
+        sweep_targets<Tr, Op, HELM, CSR, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
+                                                    t_miss);
+      if constexpr (std::is_same<Tr, F32>::value) {
+        // close pairs (rare): their terms, then, if the queue filled up, the pairs
+        // it could not take, found again
+        while (nq) {
+          close_terms<Tr, Op, HELM, CSR>(G, op, L, tb, sg, nq);
+          nq = 0;
+          if (t_miss == kNoMiss) break;
+          const int32_t tf = t_miss;
+          if (mode == kMaskAll)
+            t_miss = close_rescan<Op, CSR, kMaskAll>(G, L, X, Y, Z, nch, tb, tf, te, sg, s1, so, nq);
+          else
+            t_miss = close_rescan<Op, CSR, kMaskFirst>(G, L, X, Y, Z, nch, tb, tf, te, sg, s1, so, nq);
+        }
+      }
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
     }
     wave_lds_sync();

@@ -3,7 +3,8 @@
 The FP32 kernels take coordinate differences from fixed-point coordinates whose
 quantum is about 2^-29 h; a pair a few quanta apart would carry a large relative
 error in its term, and such a term dominates its row.  Every near pair closer
-than 2^20 quanta is therefore corrected from the FP64 coordinates at plan time.
+than 2^20 quanta therefore takes its difference from the FP64 coordinates, inside
+the kernels.
 These tests plant pairs at r = 2^-k h for k = 8 .. 40 in a 200k-point ellipsoid
 (64 points per box, box = a quarter wavelength, the density sweep's densest
 case): inside one box, and straddling a box face (where the two points are in
@@ -11,6 +12,8 @@ different boxes).  The pairs below one quantum (k >= 30) sit on one fixed-point
 position across a face, the case where an uncorrected kernel divides by zero.
 Every planted row is compared with the FP64 oracle on its own, and the whole
 output too.  Forward (both layouts), reverse pass and the matrix-core path.
+Dense clusters (hundreds of mutually close points, one of them across a box
+face) give a box more close pairs than the sweep's queue holds at once.
 """
 import math
 
@@ -136,4 +139,125 @@ def test_f64_planted(case):
     print("  FP64: planted rows max %.2e, whole %.2e" % (e_rows.max(), rel_l2(y, yref)), flush=True)
     assert e_rows.max() <= 1e-12 and rel_l2(y, yref) <= 1e-12
     assert P.info()["n_close_pairs"] == 0
+    P.close()
+
+
+def clustered(seed=5):
+    """A 30k-point sphere plus three clusters of 150 points each within 2^-20 h
+    (about 500 quanta) of an anchor, one straddling a box face: every cluster point
+    has ~149 close partners, far more than one group's close-pair queue takes at once.
+    At that distance a term from the fixed-point coordinates would be off by about
+    1e-3 of itself."""
+    base = W.sphere(30_000, 32, 2 * math.pi * 8, seed=seed, dtype=np.complex64)
+    rng = np.random.default_rng(seed)
+    h, o = base.h, base.origin
+    pts, rows = [base.xyz], []
+    n = base.n
+    for j, a in enumerate(rng.choice(n, 3, replace=False)):
+        c = base.xyz[a].copy()
+        if j == 2:  # centred on the x face of its box
+            c[0] = o[0] + (np.floor((c[0] - o[0]) / h) + 1) * h
+        cl = c + h * 2.0 ** -20 * rng.uniform(-1, 1, (150, 3))
+        pts.append(cl)
+        rows += list(range(n + 150 * j, n + 150 * (j + 1)))
+    xyz = np.ascontiguousarray(np.concatenate(pts))
+    ids = W.leaf_ids(xyz, o, h)
+    q = W.strengths(xyz.shape[0], 1, rng, np.complex64)
+    return xyz, ids, q, base.k, np.array(rows)
+
+
+def near_terms(xyz, ids, k, i):
+    """Row i's near sources (r != 0, by the definition) with G(r_ij), G'(r_ij) and
+    the differences x_i - x_j, in FP64."""
+    near = np.flatnonzero(np.all(np.abs(ids - ids[i]) <= 1, axis=1))
+    d = xyz[i] - xyz[near]
+    r = np.sqrt((d * d).sum(1))
+    m = r > 0
+    near, d, r = near[m], d[m], r[m]
+    e = np.exp(1j * k * r)
+    return near, e / (4 * np.pi * r), e * (1j * k * r - 1) / (4 * np.pi * r * r), d
+
+
+def abs_row_sums(xyz, ids, k, rows, q, g=None):
+    """Per row: sum_j |G_ij| |q_j| (forward; per column for several) and, with g, the
+    same for dq (|g_j|) and sum_j |G'_ij| |u_ij| for dx: the sizes of the terms a
+    floating-point sum of the row cannot be more exact than."""
+    fw, dqs, dxs = [], [], []
+    for i in rows:
+        near, G, Gp, d = near_terms(xyz, ids, k, i)
+        fw.append(np.abs(G) @ np.abs(q[near].reshape(near.size, -1)))
+        if g is not None:
+            dqs.append(np.abs(G) @ np.abs(g[near].reshape(near.size, -1)))
+            u = np.conj(g[i, 0]) * q[near, 0] + np.conj(g[near, 0]) * q[i, 0]
+            dxs.append(float(np.abs(Gp * u).sum()))
+    return np.array(fw), np.array(dqs), np.array(dxs)
+
+
+def err_over_abs(got, ref, rows, scale):
+    g, r = got[rows].reshape(rows.size, -1), ref[rows].reshape(rows.size, -1)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(scale.reshape(rows.size, -1), axis=1)
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    xyz, ids, q, k, rows = clustered()
+    orc = oracle.Plan(ids)
+    print("clusters: %d points, %d cluster rows" % (xyz.shape[0], rows.size), flush=True)
+    return xyz, ids, q, k, rows, orc, orc.apply(xyz, k, q)
+
+
+# Cluster rows cancel heavily (sum_j |terms| reaches hundreds of times |y_i|), so
+# their error is bounded against the size of their terms: FP32 sums of exact-
+# difference terms stay near 1e-7 of it (an FP32 emulation on the CPU gives at most
+# 9e-8); a close pair taken from the fixed-point coordinates would be ~1e-3 off.
+ABS_TOL = 1e-6
+
+
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+def test_forward_clusters(clusters, layout):
+    xyz, ids, q, k, rows, orc, yref = clusters
+    # the face cluster really spans two boxes
+    assert np.unique(ids[rows[300:], 0]).size == 2
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout=layout)
+    info = P.info()
+    y = P.apply(dev(q)).cpu().numpy().reshape(-1, 1)
+    assert np.isfinite(y).all()
+    fw, _, _ = abs_row_sums(xyz, ids, k, rows, q.astype(np.complex128))
+    e_abs = err_over_abs(y, yref, rows, fw)
+    print("  %s: %d close pairs; cluster rows: error / sum|terms| max %.2e, relative max %.2e; whole %.2e" % (
+        layout, info["n_close_pairs"], e_abs.max(), row_errors(y, yref, rows).max(), rel_l2(y, yref)), flush=True)
+    assert info["n_close_pairs"] >= 3 * 150 * 149
+    assert e_abs.max() <= ABS_TOL and rel_l2(y, yref) <= 1e-6
+    P.close()
+
+
+def test_backward_clusters(clusters):
+    xyz, ids, q, k, rows, orc, yref = clusters
+    g = W.strengths(xyz.shape[0], 1, np.random.default_rng(13), np.complex64)
+    dq_ref, dx_ref = orc.backward(xyz, k, q, g)
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout="tiles")
+    dq, dx = P.backward(dev(q), dev(g))
+    dq, dx = dq.cpu().numpy().reshape(-1, 1), dx.cpu().numpy()
+    _, sq, sx = abs_row_sums(xyz, ids, k, rows, q.astype(np.complex128), g.astype(np.complex128))
+    eq, ex = err_over_abs(dq, dq_ref, rows, sq), err_over_abs(dx, dx_ref, rows, sx)
+    print("  reverse pass, cluster rows: error / sum|terms| dq max %.2e, dx max %.2e; whole dq %.2e dx %.2e" % (
+        eq.max(), ex.max(), rel_l2(dq, dq_ref), rel_l2(dx, dx_ref)), flush=True)
+    assert eq.max() <= ABS_TOL and ex.max() <= ABS_TOL
+    assert rel_l2(dq, dq_ref) <= 1e-6 and rel_l2(dx, dx_ref) <= 1e-5
+    P.close()
+
+
+def test_matrix_cores_clusters(clusters):
+    xyz, ids, q, k, rows, orc, yref = clusters
+    m = 8
+    qm = W.strengths(xyz.shape[0], m, np.random.default_rng(17), np.complex64)
+    ref = orc.apply(xyz, k, qm)
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout="csr",
+                 max_rhs=m)
+    y = P.apply(dev(qm)).cpu().numpy()
+    fw, _, _ = abs_row_sums(xyz, ids, k, rows, qm.astype(np.complex128))
+    e_abs = err_over_abs(y, ref, rows, fw)
+    print("  matrix cores, %d columns: cluster rows error / sum|terms| max %.2e, whole %.2e" % (
+        m, e_abs.max(), rel_l2(y, ref)), flush=True)
+    assert e_abs.max() <= ABS_TOL and rel_l2(y, ref) <= 1e-6
     P.close()
