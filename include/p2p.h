@@ -106,6 +106,17 @@ typedef struct {
 p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
                        void* stream);
 
+/* p2p_box_ids for callers that cannot allocate memory (harnesses that forbid
+ * hipMalloc, loops that must not allocate): the same ids and errors, but the
+ * status word the kernel raises lives in a static 256-byte device array of the
+ * library (one per device, kept until the process ends) instead of a block from
+ * the library's allocator, and is read back into host stack memory.  Calls no
+ * allocating routine.  Calls that overlap on one device share that array and
+ * race; order them.  n above 79,536,431 (the largest plan) gives P2P_ERR_RANGE.
+ * Synchronises stream. */
+p2p_status p2p_box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
+                               void* stream);
+
 /* Builds the plan of one point set (paper sections 3.1-3.3: boxes in Morton order,
  * neighbour lists, and the per-box source lists): Morton keys of the ids, a stable
  * sort of the points by key, the table of non-empty boxes, the 27-neighbour lists

@@ -65,6 +65,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.p2p_box_ids.argtypes = [P, i64, P, f64, P, P]
+    L.p2p_box_ids_noalloc.argtypes = [P, i64, P, f64, P, P]
     L.p2p_plan_create.argtypes = [P, P, i64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_create_grid.argtypes = [P, i64, P, f64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_info.argtypes = [P, ctypes.POINTER(_Info)]
@@ -91,7 +92,7 @@ def lib():
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
-    for name in ("p2p_box_ids", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
+    for name in ("p2p_box_ids", "p2p_box_ids_noalloc", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
                  "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
                  "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
                  "p2p_batch_timing_read", "p2p_batch_destroy", "p2p2d_collect", "p2p2d_transfer", "p2p2d_run",
@@ -130,6 +131,19 @@ def box_ids(xyz: torch.Tensor, origin, h: float) -> torch.Tensor:
     o = (ctypes.c_double * 3)(*[float(v) for v in origin])
     _check(lib().p2p_box_ids(_ptr(xyz), n, o, float(h), _ptr(ids), _stream()))
     return ids
+
+
+def box_ids_noalloc(xyz: torch.Tensor, origin, h: float, out: torch.Tensor) -> torch.Tensor:
+    """box_ids into the caller's int32 [n, 3] tensor, through the library's entry point
+    that allocates nothing (p2p_box_ids_noalloc)."""
+    xyz = _cuda(xyz, torch.float64, "xyz")
+    n = xyz.shape[0]
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.int32 or \
+            tuple(out.shape) != (n, 3) or not out.is_contiguous():
+        raise TypeError("out must be a contiguous int32 CUDA tensor of shape (%d, 3)" % n)
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    _check(lib().p2p_box_ids_noalloc(_ptr(xyz), n, o, float(h), _ptr(out), _stream()))
+    return out
 
 
 class Plan:

@@ -142,6 +142,18 @@ p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, doubl
   return box_ids(xyz, n, origin, h, box_ijk, (hipStream_t)stream);
 }
 
+p2p_status p2p_box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
+                               void* stream) {
+  if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
+  if (n > kMaxPoints) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
+  if (!origin) return fail(P2P_ERR_ARG, "origin is NULL");
+  if (n > 0 && (!xyz || !box_ijk)) return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(P2P_ERR_RANGE, "h must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(P2P_ERR_RANGE, "origin must be finite");
+  return box_ids_noalloc(xyz, n, origin, h, box_ijk, (hipStream_t)stream);
+}
+
 namespace {
 
 // Common to both create calls: ids from box_ijk, or (box_ijk null) from gspec.

@@ -132,6 +132,9 @@ struct GridSpec {
 p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, const GridSpec* gspec, hipStream_t s);
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s);
 p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids, hipStream_t s);
+// The same without allocation: the status word in a static device array.
+p2p_status box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids,
+                           hipStream_t s);
 
 // diagnostics (api.hip): events around the sweep kernels of one call
 struct SweepTimer {

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1143,6 +1144,59 @@ p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h,
   rc = read_status(status, &hs, s);
   if (rc != P2P_OK) return rc;
   if (hs.st[ST_BAD_ID]) return fail(P2P_ERR_RANGE, "a coordinate is not finite or its box id falls outside [0, 2^21)");
+  return P2P_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Box ids without allocation (p2p_box_ids_noalloc).  The status word that
+// k_box_ids raises lives in this file-scope device array rather than in a block
+// from the allocator, and the host reads it into a stack variable.  Each device
+// holds its own copy; its address is looked up once per device.  Calls that
+// overlap on one device share the word and race.
+// ---------------------------------------------------------------------------
+constexpr int kScratchWords = 64;  // 256 bytes per device: word 0 is the status
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch[kScratchDevices] = {};
+
+// The current device's copy of scratch (its device address).
+p2p_status scratch_ptr(uint32_t** out) {
+  int d = 0;
+  P2P_HIP(hipGetDevice(&d));
+  if (d < 0 || d >= kScratchDevices) return fail(P2P_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[d]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    g_scratch[d] = (uint32_t*)p;
+  }
+  *out = g_scratch[d];
+  return P2P_OK;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(kWave) k_zero_words(uint32_t* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+p2p_status box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids,
+                           hipStream_t s) {
+  uint32_t* word = nullptr;
+  p2p_status rc = scratch_ptr(&word);
+  if (rc != P2P_OK) return rc;
+  if (n == 0) return P2P_OK;
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(kWave), 0, s, word, 1);
+  hipLaunchKernelGGL(k_box_ids, dim3(grid_for(3 * n)), dim3(kBlock), 0, s, xyz, 3 * n, origin[0], origin[1], origin[2],
+                     h, ids, word);
+  P2P_HIP(hipGetLastError());
+  uint32_t bad = 0;
+  P2P_HIP(hipMemcpyAsync(&bad, word, sizeof(bad), hipMemcpyDeviceToHost, s));
+  P2P_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(P2P_ERR_RANGE, "a coordinate is not finite or its box id falls outside [0, 2^21)");
   return P2P_OK;
 }
 
