@@ -77,10 +77,11 @@ struct p2p_plan_s {
   double* tile_x64;    // [3][tile_len] (FP64 plans)
   int32_t* tile_x32;   // [3][tile_len] (FP32 plans)
   // FP32 plans: per box, nonzero if the bounding box of some other neighbour box
-  // comes within kCloseQuanta + 2 quanta of the box's own on every axis.  Only
-  // such boxes can hold a pair of distinct boxes whose fixed-point difference is
-  // shorter than kCloseQuanta quanta; the kernels take the geometry of those pairs
-  // (and of close pairs inside a box) from the FP64 coordinates.
+  // comes within kCloseQuanta + 2 quanta of the box's own on every axis, or if two
+  // of the box's own points are within kCloseQuanta quanta of each other on every
+  // axis.  Only such boxes can hold a pair whose fixed-point difference is shorter
+  // than kCloseQuanta quanta; the kernels take those pairs' differences from the
+  // FP64 coordinates.
   int32_t* near;       // [B]
   int64_t n_close;     // ordered near pairs closer than kCloseQuanta quanta, -1 until counted
   // scratch for apply/backward: strengths and upstream gradients in sorted order

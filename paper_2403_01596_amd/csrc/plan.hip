@@ -854,6 +854,43 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
   }
 }
 
+// FP32 plans, after k_nbr<true>: marks box T near also when two of its own points
+// lie within kCloseQuanta quanta of each other on every axis (coincident points
+// included), which every pair whose fixed-point r2 is at most kCloseR2 does.  One
+// wavefront per box; targets in lanes, the sources of the same box walked from
+// lane reads, 64 at a time, until one pair is found.
+__global__ void __launch_bounds__(kBlock) k_own_close(const int32_t* __restrict__ sx32, int64_t n,
+                                                   const int32_t* __restrict__ box_start, int32_t nb,
+                                                   int32_t* __restrict__ near) {
+  const int32_t T = uniform((int32_t)(blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave));
+  if (T >= nb) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t b0 = box_start[T], b1 = box_start[T + 1];
+  constexpr uint32_t kTwoQ = 2u * (uint32_t)kCloseQuanta;
+  bool found = false;
+  for (int32_t tb = b0; tb < b1 && !found; tb += kWave) {
+    const int32_t ti = min(tb + lane, b1 - 1);
+    // u = x + kCloseQuanta: a source s is within kCloseQuanta on an axis iff
+    // u - s (modulo 2^32) is at most 2 kCloseQuanta
+    const uint32_t ux = (uint32_t)sx32[ti] + kCloseQuanta, uy = (uint32_t)sx32[n + ti] + kCloseQuanta,
+                   uz = (uint32_t)sx32[2 * n + ti] + kCloseQuanta;
+    for (int32_t sb = b0; sb < b1 && !found; sb += kWave) {
+      const int32_t si = min(sb + lane, b1 - 1);
+      const int32_t vx = sx32[si], vy = sx32[n + si], vz = sx32[2 * n + si];
+      const int ns = min(kWave, b1 - sb);
+      bool hit = false;
+      for (int j = 0; j < ns; ++j) {
+        const uint32_t dx = ux - (uint32_t)__builtin_amdgcn_readlane(vx, j);
+        const uint32_t dy = uy - (uint32_t)__builtin_amdgcn_readlane(vy, j);
+        const uint32_t dz = uz - (uint32_t)__builtin_amdgcn_readlane(vz, j);
+        hit = hit || (dx <= kTwoQ && dy <= kTwoQ && dz <= kTwoQ && ti != sb + j);
+      }
+      found = __ballot(hit && tb + lane < b1) != 0;
+    }
+  }
+  if (found && lane == 0) near[T] = 1;
+}
+
 // Replicated source lists: one wavefront per target box copies the points of its
 // neighbourhood into the box's contiguous list, its own points first.
 template <bool F64>
@@ -1448,6 +1485,9 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
                      dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
                      P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp, P->near, reach);
+  if (!f64)
+    hipLaunchKernelGGL(k_own_close, dim3(grid_for(B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx32, n,
+                       P->box_start, B, P->near);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)

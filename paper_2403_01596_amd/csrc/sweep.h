@@ -358,8 +358,9 @@ __device__ __forceinline__ void close_push(LdsT& L, uint64_t cm, int32_t t_off, 
 // entries [sg, s1) of the box's neighbourhood list; a target's own entry (its
 // self pair) is entry t + self_off of that list.  FP32: the close pairs met are
 // queued in L.close (nq entries); t_miss is the first target whose pairs did not
-// fit, or kNoMiss.
-template <class Tr, class Op, bool HELM, bool CSR, int MODE, class LdsT>
+// fit, or kNoMiss.  CLOSE: the box is marked near (FP32), so its masked chunks
+// may hold close pairs; other boxes' masked chunks only skip zero distances.
+template <class Tr, class Op, bool HELM, bool CSR, int MODE, bool CLOSE, class LdsT>
 __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& op, LdsT& L,
                                               const typename Tr::coord (&X)[Op::K],
                                               const typename Tr::coord (&Y)[Op::K],
@@ -395,7 +396,7 @@ __device__ __forceinline__ void sweep_targets(const SweepGeom<Tr>& G, const Op& 
         // c is a constant in each unrolled copy, so this choice costs no branch
         const bool masked = MODE == kMaskAll || (MODE == kMaskFirst && c == 0);
         if (masked) {
-          if constexpr (std::is_same<Tr, F32>::value) {
+          if constexpr (std::is_same<Tr, F32>::value && CLOSE) {
             // Pairs under kCloseQuanta quanta get no term here (rinv = 0); the
             // close ones among them (the self pair and padding entries are not)
             // are queued and taken from the FP64 coordinates after the group.
@@ -522,14 +523,14 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
       const int nch = min(K, (s1 - sg + kWave - 1) / kWave);
       if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, L.idx, lane);
       const bool first_group = sg == s0;
-      // A zero distance, or (FP32) a close pair, can only occur among the box's
-      // own points, entries [s0, s0 + n_T), unless points of distinct boxes may
-      // coincide or (FP32) the box is marked near.  Padding entries sit far away.
-      // The first-chunk form needs all own points in the first chunk of the first
-      // group.
+      // A zero distance can only occur among the box's own points, entries
+      // [s0, s0 + n_T), unless points of distinct boxes may coincide; a close pair
+      // (FP32) only in a box marked near, whose chunks all take the masked form
+      // with the close-pair test.  Padding entries sit far away.  The first-chunk
+      // form needs all own points in the first chunk of the first group.
       const bool own_here = sg < s0 + (t1 - t0);
       const int32_t so = s0 - t0;
-      const int mode = (G.may_coincide || near_box || (own_here && !(first_group && t1 - t0 <= kWave)))
+      const int mode = (G.may_coincide || (own_here && !(first_group && t1 - t0 <= kWave)))
                            ? kMaskAll
                            : (first_group ? kMaskFirst : kMaskNone);
       coord X[K], Y[K], Z[K];
@@ -568,27 +569,27 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
         }
       }
       int32_t nq = 0, t_miss = kNoMiss;
-      if (mode == kMaskAll)
-        sweep_targets<Tr, Op, HELM, CSR, kMaskAll>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
-                                                   t_miss);
+      if (std::is_same<Tr, F32>::value && near_box)
+        sweep_targets<Tr, Op, HELM, CSR, kMaskAll, true>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1,
+                                                         so, nq, t_miss);
+      else if (mode == kMaskAll)
+        sweep_targets<Tr, Op, HELM, CSR, kMaskAll, false>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1,
+                                                          so, nq, t_miss);
       else if (mode == kMaskFirst)
-        sweep_targets<Tr, Op, HELM, CSR, kMaskFirst>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
-                                                     t_miss);
+        sweep_targets<Tr, Op, HELM, CSR, kMaskFirst, false>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1,
+                                                            so, nq, t_miss);
       else
-        sweep_targets<Tr, Op, HELM, CSR, kMaskNone>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1, so, nq,
-                                                    t_miss);
+        sweep_targets<Tr, Op, HELM, CSR, kMaskNone, false>(G, op, L, X, Y, Z, P, nch, tb, te, first_group, sg, s1,
+                                                           so, nq, t_miss);
       if constexpr (std::is_same<Tr, F32>::value) {
-        // close pairs (rare): their terms, then, if the queue filled up, the pairs
-        // it could not take, found again
+        // close pairs (marked boxes only, rare): their terms, then, if the queue
+        // filled up, the pairs it could not take, found again
         while (nq) {
           close_terms<Tr, Op, HELM, CSR>(G, op, L, tb, sg, nq);
           nq = 0;
           if (t_miss == kNoMiss) break;
           const int32_t tf = t_miss;
-          if (mode == kMaskAll)
-            t_miss = close_rescan<Op, CSR, kMaskAll>(G, L, X, Y, Z, nch, tb, tf, te, sg, s1, so, nq);
-          else
-            t_miss = close_rescan<Op, CSR, kMaskFirst>(G, L, X, Y, Z, nch, tb, tf, te, sg, s1, so, nq);
+          t_miss = close_rescan<Op, CSR, kMaskAll>(G, L, X, Y, Z, nch, tb, tf, te, sg, s1, so, nq);
         }
       }
       if (CSR) wave_lds_sync();  // the index buffer is refilled for the next group
