@@ -335,6 +335,158 @@ def measure_layouts(p2p, W, torch, reps, with_oracle):
     return out
 
 
+def measure_paper_2d(p2p, torch, reps, with_oracle, max_layout_bytes=4e9, max_boxes=4 ** 12):
+    """The paper's own grid (section 4.6, eq. 38): N = 4^L points uniform on the unit
+    square, L = 4..11, quadtree height L + i, i = -3..3 (D = 4^(1-i) points per box,
+    empty boxes included), CT = 15, one real potential per point, the 2-D log kernel.
+    Per cell: the Indexing and Repetition layouts' host collection, host-to-device
+    transfer and kernel (section 3.2, 3.3), the library's own plan and sweep of the
+    same points, and, for N <= 65536, the oracle on one core (the paper's CPU
+    baseline).  Cells whose Repetition layout would exceed max_layout_bytes, or whose
+    tree has more than max_boxes leaves, are left out (as the paper left out cells
+    beyond its resources).  Then the paper's model (section 3.4) re-fitted on these
+    measurements: lambda_RAM from eq. 16, lambda_GPU from eq. 28, and alpha, beta,
+    gamma of eq. 36 by non-negative least squares."""
+    import numpy as np
+    CT = 15
+    rows = []
+    dev = torch.device("cuda:0")
+
+    def kernel_ms(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for L in range(4, 12):
+        N = 4 ** L
+        rng = np.random.default_rng(L)
+        xy = rng.random((N, 2))
+        q = rng.standard_normal(N)
+        xyz = np.zeros((N, 3))
+        xyz[:, :2] = xy
+        ref = None
+        for i in range(-3, 4):
+            level = L + i
+            boxes = 4 ** (level - 1)
+            D = N / boxes
+            row = {"L": L, "i": i, "N": N, "level": level, "boxes": boxes, "D": D}
+            # Repetition record: 3 + 27 CT doubles, or 3 + 3 x the largest neighbourhood
+            est = N * 8 * (3 + 3 * 9 * max(CT, int(np.ceil(2.5 * D))))
+            if boxes > max_boxes or est > max_layout_bytes:
+                row["skipped"] = "Repetition layout ~%.1f GB or %d boxes" % (est / 1e9, boxes)
+                rows.append(row)
+                continue
+            if with_oracle and N <= 65536:
+                import oracle
+                t0 = time.perf_counter()
+                ref = oracle.apply2d(xy, q, level, threads=1)
+                row["baseline_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+            else:
+                ref = None
+            for method in ("indexing", "repetition"):
+                Q = p2p.Quad2D(method, xy, q, level, CT)
+                inf = Q.info()
+                trs = []
+                for _ in range(3):
+                    Q.transfer()
+                    trs.append(Q.info()["transfer_ms"])
+                y = torch.empty(N, dtype=torch.float64, device=dev)
+                k_ms = kernel_ms(lambda: Q.run(y))
+                m = {"collect_ms": round(inf["collect_ms"], 3), "transfer_ms": round(float(np.median(trs)), 3),
+                     "kernel_ms": round(k_ms, 4), "layout_bytes": inf["layout_bytes"], "t_max": inf["t_max"]}
+                if ref is not None:
+                    yy = y.cpu().numpy()
+                    m["rel_err"] = float(np.linalg.norm(yy - ref) / np.linalg.norm(ref))
+                row[method] = m
+                row["t"] = inf["t_max"]
+                Q.close()
+            # the library's own route: device plan of (x, y, 0), FP64 sweep with the 2-D kernel
+            xd = torch.from_numpy(xyz).to(dev)
+            qd = torch.from_numpy(q).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = p2p.Plan.from_grid(xd, (0.0, 0.0, 0.0), 2.0 ** (1 - level), 0.0, dtype=torch.complex128, layout="csr")
+            plan_ms = (time.perf_counter() - t0) * 1e3
+            yo = torch.empty(N, dtype=torch.float64, device=dev)
+            a_ms = kernel_ms(lambda: P.apply_log2d(qd, yo))
+            row["library"] = {"plan_ms": round(plan_ms, 3), "apply_ms": round(a_ms, 4)}
+            if ref is not None:
+                yy = yo.cpu().numpy()
+                row["library"]["rel_err"] = float(np.linalg.norm(yy - ref) / np.linalg.norm(ref))
+            P.close()
+            ind, rep = row["indexing"], row["repetition"]
+            tot = lambda m: m["collect_ms"] + m["transfer_ms"] + m["kernel_ms"]
+            row["X_total"] = tot(ind) / tot(rep)
+            row["X_collect"] = ind["collect_ms"] / rep["collect_ms"]
+            row["X_transfer"] = ind["transfer_ms"] / rep["transfer_ms"]
+            row["X_kernel"] = ind["kernel_ms"] / rep["kernel_ms"]
+            row["library_vs_repetition"] = tot(rep) / (row["library"]["plan_ms"] + row["library"]["apply_ms"])
+            rows.append(row)
+            log("paper 2-D L=%d i=%+d N=%d D=%.4g t=%d: collect %.1f / %.1f ms, transfer %.2f / %.2f, kernel %.3f / "
+                "%.3f (Indexing / Repetition), Repetition %.2fx; library plan %.2f + sweep %.3f ms" % (
+                    L, i, N, D, row["t"], ind["collect_ms"], rep["collect_ms"], ind["transfer_ms"],
+                    rep["transfer_ms"], ind["kernel_ms"], rep["kernel_ms"], row["X_total"],
+                    row["library"]["plan_ms"], row["library"]["apply_ms"]))
+    fit = paper_model_fit(rows)
+    done = [r for r in rows if "X_total" in r]
+    best = max((r for r in done if r["N"] >= 16384), key=lambda r: r["X_total"])
+    return {"workload": "unit square, N = 4^L (L = 4..11), height L + i (i = -3..3), CT = 15, 2-D log kernel, FP64",
+            "cells": rows, "fit": fit,
+            "repetition_over_indexing_max_N_ge_16384": {"X_total": round(best["X_total"], 3), "L": best["L"],
+                                                        "i": best["i"]},
+            "paper_repetition_over_indexing": "7-13x for N >= 16,000 and i >= 2 (context only: other hardware)"}
+
+
+def paper_model_fit(rows, n_min=4096):
+    """The paper's speedup model (section 3.4) against the measured cells with
+    N >= n_min (smaller cells take microseconds, where launch and timer overheads
+    dominate).  Eq. 36 models X_total = alpha X_collect + gamma X_transfer + beta
+    X_kernel with constant coefficients: fitted here by non-negative least squares,
+    as the paper does.  Exactly, X_total = sum over phases of (Repetition's time in
+    the phase / its total) x X_phase, so each cell's own time shares are the
+    coefficients that make eq. 36 exact; their means are reported beside the fit.
+    lambda_RAM (eq. 16) and lambda_GPU (eq. 28) per cell, by density D."""
+    import numpy as np
+    from scipy.optimize import nnls
+    done = [r for r in rows if "X_total" in r and r["N"] >= n_min]
+    A = np.array([[r["X_collect"], r["X_kernel"], r["X_transfer"]] for r in done])
+    b = np.array([r["X_total"] for r in done])
+    coef, _ = nnls(A, b)
+    pred = A @ coef
+    tot = lambda m: m["collect_ms"] + m["transfer_ms"] + m["kernel_ms"]
+    shares = np.array([[r["repetition"]["collect_ms"] / tot(r["repetition"]),
+                        r["repetition"]["kernel_ms"] / tot(r["repetition"]),
+                        r["repetition"]["transfer_ms"] / tot(r["repetition"])] for r in done])
+    by_d = {}
+    for r in done:
+        d = by_d.setdefault("%g" % r["D"], {"lambda_RAM": [], "lambda_GPU": [], "X_total": []})
+        d["lambda_RAM"].append(r["X_collect"] * 21.6 * r["t"] * r["D"])
+        d["lambda_GPU"].append(r["X_kernel"] * r["N"] * r["D"] / (55.3 * r["t"]))
+        d["X_total"].append(r["X_total"])
+    med = lambda v: round(float(np.median(v)), 4)
+    return {"cells": len(done), "N_min": n_min,
+            "nnls": {"alpha": round(float(coef[0]), 4), "beta": round(float(coef[1]), 4),
+                     "gamma": round(float(coef[2]), 4),
+                     "rel_residual": round(float(np.linalg.norm(pred - b) / np.linalg.norm(b)), 4)},
+            "time_shares_mean": {"alpha": round(float(shares[:, 0].mean()), 4),
+                                 "beta": round(float(shares[:, 1].mean()), 4),
+                                 "gamma": round(float(shares[:, 2].mean()), 4)},
+            "by_density": {k: {"lambda_RAM_median": med(v["lambda_RAM"]), "lambda_GPU_median": med(v["lambda_GPU"]),
+                               "X_total_median": med(v["X_total"]), "cells": len(v["X_total"])}
+                           for k, v in sorted(by_d.items(), key=lambda kv: -float(kv[0]))},
+            "paper": {"alpha": 0.82, "beta": 0.09, "gamma": 0.18, "lambda_RAM": "75-180, mean 108",
+                      "lambda_GPU": "about 640", "hardware": "Core i7 7th gen + GeForce GTX 1050"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +506,11 @@ def main():
                     help="only build the plan and run the apply --apply-reps times (for counter runs)")
     ap.add_argument("--sweep-precision", choices=["f32", "f64"], default="f32",
                     help="precision of the plan that --sweep-only runs")
+    ap.add_argument("--paper-2d", action="store_true",
+                    help="only the paper's 2-D experiment grid (Indexing vs Repetition) and the model re-fit")
+    ap.add_argument("--paper-2d-cell", default=None, metavar="L,i",
+                    help="only the two 2-D layouts' kernels on one cell of that grid, 5 runs each "
+                         "(for counter runs)")
     ap.add_argument("--backward-only", action="store_true",
                     help="only run the reverse pass on its 500k-point cube, FP32 then FP64, "
                          "--apply-reps times each (for counter runs)")
@@ -378,6 +535,25 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copied 3 x %d bytes" % (a.numel() * 4))
+        return 0
+
+    if args.paper_2d_cell:
+        L, i = (int(v) for v in args.paper_2d_cell.split(","))
+        rng = np.random.default_rng(L)
+        xy, q = rng.random((4 ** L, 2)), rng.standard_normal(4 ** L)
+        for method in ("indexing", "repetition"):
+            Q = p2p.Quad2D(method, xy, q, L + i, 15)
+            Q.transfer()
+            y = torch.empty(4 ** L, dtype=torch.float64, device="cuda")
+            for _ in range(5):
+                Q.run(y)
+            torch.cuda.synchronize()
+            log("paper 2-D cell L=%d i=%d: %s kernel run 5 times" % (L, i, method))
+            Q.close()
+        return 0
+
+    if args.paper_2d:
+        print(json.dumps(measure_paper_2d(p2p, torch, 5, not args.no_cpu)))
         return 0
 
     if args.mrhs_only:
