@@ -106,6 +106,19 @@ typedef struct {
 p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
                        void* stream);
 
+/* The leaf level for a clustering threshold (paper section 3.1: the tree height is
+ * raised, from a starting value, until no leaf box holds more than CT points).
+ * Height L divides the cube [origin, origin + size)^3 into 2^(L-1) boxes per axis,
+ * box size h = size 2^(1-L), L in [1, 22].  Returns in *level the smallest
+ * L >= min_level whose boxes hold at most ct points each, in *h its box size and
+ * in *t_max its largest occupancy; p2p_box_ids with (origin, *h) then gives ids of
+ * exactly that occupancy.  origin: host double[3]; level, h, t_max: host.
+ * P2P_ERR_RANGE if a point lies outside the cube or is not finite, or if even
+ * height 22 leaves more than ct points in one box (coincident points; *level, *h
+ * and *t_max then describe height 22).  Synchronises stream. */
+p2p_status p2p_leaf_level(const double* xyz, int64_t n, const double* origin, double size, int32_t ct,
+                          int32_t min_level, int32_t* level, double* h, int32_t* t_max, void* stream);
+
 /* p2p_box_ids for callers that cannot allocate memory (harnesses that forbid
  * hipMalloc, loops that must not allocate): the same ids and errors, but the
  * status word the kernel raises lives in a static 256-byte device array of the

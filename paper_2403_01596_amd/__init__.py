@@ -66,6 +66,8 @@ def lib():
     P, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.p2p_box_ids.argtypes = [P, i64, P, f64, P, P]
     L.p2p_box_ids_noalloc.argtypes = [P, i64, P, f64, P, P]
+    L.p2p_leaf_level.argtypes = [P, i64, P, f64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(f64),
+                                 ctypes.POINTER(i32), P]
     L.p2p_plan_create.argtypes = [P, P, i64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_create_grid.argtypes = [P, i64, P, f64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_info.argtypes = [P, ctypes.POINTER(_Info)]
@@ -92,7 +94,7 @@ def lib():
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
-    for name in ("p2p_box_ids", "p2p_box_ids_noalloc", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
+    for name in ("p2p_box_ids", "p2p_box_ids_noalloc", "p2p_leaf_level", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
                  "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
                  "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
                  "p2p_batch_timing_read", "p2p_batch_destroy", "p2p2d_collect", "p2p2d_transfer", "p2p2d_run",
@@ -131,6 +133,18 @@ def box_ids(xyz: torch.Tensor, origin, h: float) -> torch.Tensor:
     o = (ctypes.c_double * 3)(*[float(v) for v in origin])
     _check(lib().p2p_box_ids(_ptr(xyz), n, o, float(h), _ptr(ids), _stream()))
     return ids
+
+
+def leaf_level(xyz: torch.Tensor, origin, size: float, ct: int = 15, min_level: int = 1):
+    """The tree height whose leaf boxes (2^(L-1) per axis over the cube [origin,
+    origin + size)^3) hold at most ct points each, smallest from min_level on:
+    returns (level, h, t_max).  The paper's clustering-threshold loop (section 3.1)."""
+    xyz = _cuda(xyz, torch.float64, "xyz")
+    o = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    lv, h, t = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    _check(lib().p2p_leaf_level(_ptr(xyz), xyz.shape[0], o, float(size), int(ct), int(min_level), ctypes.byref(lv),
+                                ctypes.byref(h), ctypes.byref(t), _stream()))
+    return lv.value, h.value, t.value
 
 
 def box_ids_noalloc(xyz: torch.Tensor, origin, h: float, out: torch.Tensor) -> torch.Tensor:

@@ -142,6 +142,20 @@ p2p_status p2p_box_ids(const double* xyz, int64_t n, const double* origin, doubl
   return box_ids(xyz, n, origin, h, box_ijk, (hipStream_t)stream);
 }
 
+p2p_status p2p_leaf_level(const double* xyz, int64_t n, const double* origin, double size, int32_t ct,
+                          int32_t min_level, int32_t* level, double* h, int32_t* t_max, void* stream) {
+  if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
+  if (!origin || !level || !h || !t_max) return fail(P2P_ERR_ARG, "origin, level, h or t_max is NULL");
+  if (n > 0 && !xyz) return fail(P2P_ERR_ARG, "xyz is NULL");
+  if (n > kMaxPoints) return fail(P2P_ERR_RANGE, "n exceeds 79,536,431 points");
+  if (!(size > 0.0) || !std::isfinite(size)) return fail(P2P_ERR_RANGE, "size must be finite and > 0");
+  if (ct < 1) return fail(P2P_ERR_RANGE, "ct must be >= 1");
+  if (min_level < 1 || min_level > 22) return fail(P2P_ERR_RANGE, "min_level must be in [1, 22]");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(P2P_ERR_RANGE, "origin must be finite");
+  return leaf_level(xyz, n, origin, size, ct, min_level, level, h, t_max, (hipStream_t)stream);
+}
+
 p2p_status p2p_box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* box_ijk,
                                void* stream) {
   if (n < 0) return fail(P2P_ERR_ARG, "n < 0");

@@ -132,6 +132,9 @@ struct GridSpec {
 // ids null: computed from xyz with gspec.
 p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, const GridSpec* gspec, hipStream_t s);
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s);
+// The leaf height for a clustering threshold (p2p_leaf_level).
+p2p_status leaf_level(const double* xyz, int64_t n, const double* origin, double size, int32_t ct, int32_t lmin,
+                      int32_t* level, double* h, int32_t* t_max, hipStream_t s);
 p2p_status box_ids(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids, hipStream_t s);
 // The same without allocation: the status word in a static device array.
 p2p_status box_ids_noalloc(const double* xyz, int64_t n, const double* origin, double h, int32_t* ids,

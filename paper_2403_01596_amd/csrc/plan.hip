@@ -1237,6 +1237,108 @@ p2p_status box_ids_noalloc(const double* xyz, int64_t n, const double* origin, d
   return P2P_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Leaf level from the clustering threshold (paper, section 3.1: the tree height is
+// raised until no leaf box holds more than CT points).  Height L has 2^(L-1) boxes
+// per axis over the cube [origin, origin + size)^3, box size h = size 2^(1-L).  The
+// points' keys on the finest grid (2^21 per axis, height 22) are sorted once; the
+// boxes of height L are then the runs of equal key >> 3 (22 - L).  A point's id at
+// height L, floor((x - o) / h), equals its finest id shifted right by 22 - L (h is
+// size times a power of two), so the ids p2p_box_ids gives for the returned h have
+// exactly the occupancy found here.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_fine_keys(const double* __restrict__ xyz, int64_t n, double ox, double oy,
+                                                   double oz, double size, uint64_t* __restrict__ key,
+                                                   uint32_t* __restrict__ bad) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const double o[3] = {ox, oy, oz};
+  uint32_t id[3];
+  bool out = false;
+  for (int a = 0; a < 3; ++a) {
+    const double v = (xyz[3 * p + a] - o[a]) / size;
+    out = out || !(v >= 0.0 && v < 1.0);
+    id[a] = out ? 0u : (uint32_t)floor(ldexp(v, kIdBits));
+  }
+  if (out) atomicOr(bad, 1u);
+  key[p] = morton3(id[0], id[1], id[2]);
+}
+
+// Largest run of sorted keys equal after >> shift: every run start finds its run's
+// end by binary search; the maximum over the launch lands in *tmax.
+__global__ void __launch_bounds__(kBlock) k_level_tmax(const uint64_t* __restrict__ key, int64_t n, int shift,
+                                                    uint32_t* __restrict__ tmax) {
+  __shared__ uint32_t lds[kBlock / kWave];
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t len = 0;
+  if (p < n) {
+    const uint64_t pre = key[p] >> shift;
+    if (p == 0 || (key[p - 1] >> shift) != pre) {
+      const uint64_t end_key = (pre + 1) << shift;  // first key of the next box (at most 2^63)
+      int64_t lo = p + 1, hi = n;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < end_key) lo = mid + 1;
+        else hi = mid;
+      }
+      len = (uint32_t)std::min<int64_t>(lo - p, 0xffffffffll);
+    }
+  }
+  const uint32_t m = block_combine63(wave_max63(len), lds, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
+  if (threadIdx.x == 0 && m) atomicMax(tmax, m);
+}
+
+p2p_status leaf_level(const double* xyz, int64_t n, const double* origin, double size, int32_t ct, int32_t lmin,
+                      int32_t* level, double* h, int32_t* t_max, hipStream_t s) {
+  constexpr int kTop = kIdBits + 1;  // height of the finest grid
+  *level = lmin;
+  *h = std::ldexp(size, 1 - lmin);
+  *t_max = 0;
+  if (n == 0) return P2P_OK;
+  const int64_t g_rs = grid_for(n, kRsTile);
+  const int64_t scan_parts = grid_for(std::max<int64_t>(256 * g_rs, n + 1), kScanTile);
+  uint64_t *k0 = nullptr, *kx = nullptr;
+  int32_t *v0 = nullptr, *vx = nullptr;
+  uint32_t *hist = nullptr, *part = nullptr, *word = nullptr;
+  auto carve = [&](Bump& b) {
+    word = b.take<uint32_t>(64);
+    k0 = b.take<uint64_t>(n);
+    kx = b.take<uint64_t>(n);
+    v0 = b.take<int32_t>(n);
+    vx = b.take<int32_t>(n);
+    hist = b.take<uint32_t>(256 * g_rs);
+    part = b.take<uint32_t>(std::max<int64_t>(scan_parts, 256));
+  };
+  ScopedBlock blk(s);
+  p2p_status rc = dev_alloc(&blk.p, measure(carve));
+  if (rc != P2P_OK) return rc;
+  {
+    Bump b{(char*)blk.p, 0};
+    carve(b);
+  }
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, word, (int64_t)64, nullptr, nullptr, (int64_t)0, nullptr,
+                     (int64_t)0);
+  hipLaunchKernelGGL(k_fine_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, xyz, n, origin[0], origin[1], origin[2],
+                     size, k0, word);
+  SortedKeys sk;
+  rc = radix_sort(k0, v0, kx, vx, n, 3 * kIdBits, hist, part, &sk, s);
+  if (rc != P2P_OK) return rc;
+  uint32_t host[kTop + 2] = {};
+  for (int L = lmin; L <= kTop; ++L)
+    hipLaunchKernelGGL(k_level_tmax, dim3(grid_for(n)), dim3(kBlock), 0, s, sk.k64, n, 3 * (kTop - L), word + L);
+  P2P_HIP(hipGetLastError());
+  P2P_HIP(hipMemcpyAsync(host, word, sizeof(host), hipMemcpyDeviceToHost, s));
+  P2P_HIP(hipStreamSynchronize(s));
+  if (host[0]) return fail(P2P_ERR_RANGE, "a point lies outside [origin, origin + size) or is not finite");
+  for (int L = lmin; L <= kTop; ++L) {
+    *level = L;
+    *h = std::ldexp(size, 1 - L);
+    *t_max = (int32_t)host[L];
+    if ((int64_t)host[L] <= ct) return P2P_OK;
+  }
+  return fail(P2P_ERR_RANGE, "more than ct points share one box of the finest grid (coincident points)");
+}
+
 p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, const GridSpec* gspec, hipStream_t s) {
   const int64_t n = P->n;
   const bool f64 = P->precision == P2P_C128;
