@@ -96,6 +96,8 @@ typedef struct {
   int64_t n_close_pairs; /* FP32 plans: ordered near pairs closer than 2^20 quanta
                             (r != 0), whose kernel values the kernels take from the
                             FP64 coordinates; 0 for FP64 plans                     */
+  int64_t n_targets;    /* plans of distinct sets (p2p_plan_create_st): targets, the
+                           first n_targets of n_points; otherwise n_points         */
 } p2p_info;
 
 /* Leaf-box ids from positions: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h),
@@ -149,6 +151,21 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
  * falls outside [0, 2^21).  Otherwise as p2p_plan_create. */
 p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* origin, double h, double k,
                                 const p2p_opts* opts, void* stream, p2p_plan* out);
+
+/* A plan whose targets and sources are distinct point sets (the paper keeps the
+ * two in separate arrays, section 3.1):
+ *     y[i,c] = sum over sources j in the 27 boxes around target i's box, with
+ *              t_i != s_j, of G(|t_i - s_j|) q[j,c].
+ * targets [n_targets,3], sources [n_sources,3] float64, device; both on the leaf
+ * grid (origin, h) as in p2p_plan_create_grid.  p2p_apply on such a plan takes q
+ * [n_sources, nrhs] (source order) and writes y [n_targets, nrhs] (target order),
+ * through the single-column sweep for any nrhs; p2p_apply_backward, batches and
+ * p2p_apply_log2d refuse it (P2P_ERR_ARG).  p2p_plan_export gives the tables of the
+ * combined set, targets first (perm entries below n_targets are targets).
+ * Otherwise as p2p_plan_create_grid. */
+p2p_status p2p_plan_create_st(const double* targets, int64_t n_targets, const double* sources, int64_t n_sources,
+                              const double* origin, double h, double k, const p2p_opts* opts, void* stream,
+                              p2p_plan* out);
 
 /* Plan statistics (paper section 3.2: t, the largest box occupancy; section 3.4.1:
  * D, the mean number of points per box).  n_pairs, n_zero_pairs and n_close_pairs

@@ -43,7 +43,7 @@ class _Info(ctypes.Structure):
                 ("n_slots", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_zero_pairs", ctypes.c_int64),
                 ("tile_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("t_max", ctypes.c_int32),
                 ("quantum_exp", ctypes.c_int32), ("d_mean", ctypes.c_double), ("max_sep", ctypes.c_double),
-                ("n_close_pairs", ctypes.c_int64)]
+                ("n_close_pairs", ctypes.c_int64), ("n_targets", ctypes.c_int64)]
 
 
 class _Info2D(ctypes.Structure):
@@ -70,6 +70,8 @@ def lib():
                                  ctypes.POINTER(i32), P]
     L.p2p_plan_create.argtypes = [P, P, i64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_create_grid.argtypes = [P, i64, P, f64, f64, ctypes.POINTER(_Opts), P, ctypes.POINTER(ctypes.c_void_p)]
+    L.p2p_plan_create_st.argtypes = [P, i64, P, i64, P, f64, f64, ctypes.POINTER(_Opts), P,
+                                     ctypes.POINTER(ctypes.c_void_p)]
     L.p2p_plan_info.argtypes = [P, ctypes.POINTER(_Info)]
     L.p2p_plan_export.argtypes = [P, P, P, P, P, P]
     L.p2p_apply.argtypes = [P, P, P, i32, ctypes.c_int, P]
@@ -94,7 +96,7 @@ def lib():
     L.p2p_last_error.restype = ctypes.c_char_p
     L.p2p_status_str.restype = ctypes.c_char_p
     L.p2p_status_str.argtypes = [ctypes.c_int]
-    for name in ("p2p_box_ids", "p2p_box_ids_noalloc", "p2p_leaf_level", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
+    for name in ("p2p_box_ids", "p2p_box_ids_noalloc", "p2p_leaf_level", "p2p_plan_create", "p2p_plan_create_grid", "p2p_plan_create_st", "p2p_plan_info", "p2p_plan_export", "p2p_apply",
                  "p2p_apply_backward", "p2p_plan_destroy", "p2p_plan_timing", "p2p_plan_timing_read",
                  "p2p_batch_create", "p2p_batch_apply", "p2p_batch_tune", "p2p_batch_timing",
                  "p2p_batch_timing_read", "p2p_batch_destroy", "p2p2d_collect", "p2p2d_transfer", "p2p2d_run",
@@ -178,12 +180,22 @@ class Plan:
         self.layout = layout
         self.k = float(k)
         self.n = xyz.shape[0]
+        sets = getattr(self, "_sets", None)  # (n_targets, sources) from from_sets
+        self.n_targets = self.n if sets is None else sets[0]
+        self.n_sources = self.n if sets is None else sets[1].shape[0]
         self.max_rhs = int(max_rhs)
         self.device = xyz.device
         opts = _Opts(P2P_C64 if dtype == torch.complex64 else P2P_C128, LAYOUTS[layout], self.max_rhs, 0,
                      tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
-        if ids is None:  # leaf grid given by from_grid
+        if sets is not None:  # distinct target and source sets (from_sets): xyz holds the targets
+            src = _cuda(sets[1], torch.float64, "sources")
+            org = (ctypes.c_double * 3)(*self._grid[0])
+            _check(lib().p2p_plan_create_st(_ptr(xyz), self.n_targets, _ptr(src), self.n_sources, org,
+                                            float(self._grid[1]), self.k, ctypes.byref(opts), _stream(),
+                                            ctypes.byref(h)))
+            self.n = self.n_targets + self.n_sources
+        elif ids is None:  # leaf grid given by from_grid
             org = (ctypes.c_double * 3)(*self._grid[0])
             _check(lib().p2p_plan_create_grid(_ptr(xyz), self.n, org, float(self._grid[1]), self.k,
                                               ctypes.byref(opts), _stream(), ctypes.byref(h)))
@@ -199,6 +211,22 @@ class Plan:
         self = cls.__new__(cls)
         self._grid = ([float(v) for v in origin], float(h))
         cls.__init__(self, xyz, None, k, dtype=dtype, layout=layout, max_rhs=max_rhs, tune_cache=tune_cache)
+        return self
+
+    @classmethod
+    def from_sets(cls, targets: torch.Tensor, sources: torch.Tensor, origin, h: float, k: float,
+                  dtype=torch.complex64, layout: str = "tiles", max_rhs: int = 1) -> "Plan":
+        """A plan whose targets and sources are distinct point sets, both on the leaf
+        grid (origin, h): apply(q) takes q [n_sources(, m)] and returns y
+        [n_targets(, m)].  No reverse pass."""
+        self = cls.__new__(cls)
+        self._grid = ([float(v) for v in origin], float(h))
+        sources = _cuda(sources, torch.float64, "sources")
+        if sources.dim() != 2 or sources.shape[1] != 3:
+            raise ValueError("sources must be [n, 3]")
+        self._sets = (targets.shape[0], sources)
+        cls.__init__(self, targets, None, k, dtype=dtype, layout=layout, max_rhs=max_rhs)
+        self._sets = None
         return self
 
     @property
@@ -269,23 +297,28 @@ class Plan:
         _check(lib().p2p_plan_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(calls)))
         return ms.value, calls.value
 
-    def _rhs(self, q: torch.Tensor, name="q"):
+    def _rhs(self, q: torch.Tensor, name="q", rows=None):
         q = _cuda(q, self.dtype, name)
-        if q.shape[0] != self.n or q.dim() not in (1, 2):
-            raise ValueError("%s must be [n] or [n, m]" % name)
+        rows = self.n if rows is None else rows
+        if q.dim() not in (1, 2) or q.shape[0] != rows:
+            raise ValueError("%s must be [%d] or [%d, m]" % (name, rows, rows))
         return q
 
     def apply(self, q: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        q = self._rhs(q)
+        q = self._rhs(q, rows=self.n_sources)
         m = 1 if q.dim() == 1 else q.shape[1]
-        y = torch.empty_like(q) if out is None else out
-        if y.shape != q.shape or y.dtype != q.dtype or not y.is_contiguous():
-            raise ValueError("out must be a contiguous tensor shaped like q")
+        shape = (self.n_targets,) + tuple(q.shape[1:])
+        y = torch.empty(shape, dtype=q.dtype, device=q.device) if out is None else out
+        if tuple(y.shape) != shape or y.dtype != q.dtype or not y.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (q.dtype, shape))
         dt = P2P_C64 if self.dtype == torch.complex64 else P2P_C128
         _check(lib().p2p_apply(self.handle, _ptr(q), _ptr(y), m, dt, _stream()))
         return y
 
     def backward(self, q: torch.Tensor, grad_y: torch.Tensor, want_dq: bool = True, want_dx: bool = True):
+        dt = P2P_C64 if self.dtype == torch.complex64 else P2P_C128
+        if self.n_targets != self.n or self.n_sources != self.n:  # distinct sets: the library refuses
+            _check(lib().p2p_apply_backward(self.handle, None, None, None, None, 1, dt, _stream()))
         q = self._rhs(q)
         gy = self._rhs(grad_y, "grad_y")
         if gy.shape != q.shape:

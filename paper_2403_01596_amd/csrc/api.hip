@@ -170,9 +170,10 @@ p2p_status p2p_box_ids_noalloc(const double* xyz, int64_t n, const double* origi
 
 namespace {
 
-// Common to both create calls: ids from box_ijk, or (box_ijk null) from gspec.
+// Common to the create calls: ids from box_ijk, or (box_ijk null) from gspec.
+// n_targets >= 0: distinct sets, the first n_targets points are the targets.
 p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::GridSpec* gspec, int64_t n, double k,
-                       const p2p_opts* opts, void* stream, p2p_plan* out) {
+                       const p2p_opts* opts, void* stream, p2p_plan* out, int64_t n_targets = -1) {
   if (!out) return fail(P2P_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (n < 0) return fail(P2P_ERR_ARG, "n < 0");
@@ -197,6 +198,8 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   P->precision = o.precision;
   P->layout = o.layout;
   P->max_rhs = o.max_rhs;
+  P->distinct_sets = n_targets >= 0;
+  P->n_targets = P->distinct_sets ? n_targets : n;
   P->n_pairs = -1;
   P->n_zero = -1;
   P->n_close = -1;
@@ -212,7 +215,7 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
     rc = fail(P2P_ERR_HIP, "hipEventCreateWithFlags failed");
   }
   if (rc == P2P_OK) rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, (hipStream_t)stream);
-  if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin) {
+  if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin && !P->distinct_sets) {
     rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
     if (rc == P2P_OK && o.tune_cache) batch_use_cache(P->self_batch, o.tune_cache);
   }
@@ -235,6 +238,46 @@ p2p_status p2p_plan_create(const double* xyz, const int32_t* box_ijk, int64_t n,
     return fail(P2P_ERR_ARG, "xyz or box_ijk is NULL");
   }
   return create_plan(xyz, box_ijk, nullptr, n, k, opts, stream, out);
+}
+
+p2p_status p2p_plan_create_st(const double* targets, int64_t n_targets, const double* sources, int64_t n_sources,
+                              const double* origin, double h, double k, const p2p_opts* opts, void* stream,
+                              p2p_plan* out) {
+  if (out) *out = nullptr;
+  if (!out) return fail(P2P_ERR_ARG, "out is NULL");
+  if (n_targets < 0 || n_sources < 0) return fail(P2P_ERR_ARG, "n_targets or n_sources < 0");
+  if ((n_targets > 0 && !targets) || (n_sources > 0 && !sources)) return fail(P2P_ERR_ARG, "targets or sources is NULL");
+  if (!origin) return fail(P2P_ERR_ARG, "origin is NULL");
+  if (n_targets + n_sources > kMaxPoints) return fail(P2P_ERR_RANGE, "more than 79,536,431 points in all");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(P2P_ERR_RANGE, "h must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(P2P_ERR_RANGE, "origin must be finite");
+  const int64_t n = n_targets + n_sources;
+  const hipStream_t s = (hipStream_t)stream;
+  // one point array, targets first: the plan's boxes then list each box's targets
+  // before its sources
+  void* both = nullptr;
+  if (n > 0) {
+    both = dmem_alloc(sizeof(double) * 3 * (size_t)n);
+    if (!both) return fail(P2P_ERR_NOMEM, "device allocation failed");
+    hipError_t e = hipSuccess;
+    if (n_targets > 0) e = hipMemcpyAsync(both, targets, sizeof(double) * 3 * n_targets, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && n_sources > 0)
+      e = hipMemcpyAsync((double*)both + 3 * n_targets, sources, sizeof(double) * 3 * n_sources,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      dmem_free(both);
+      return hip_fail(e, "hipMemcpyAsync");
+    }
+  }
+  const p2p::GridSpec g{{origin[0], origin[1], origin[2]}, h};
+  const p2p_status rc = create_plan((const double*)both, nullptr, &g, n, k, opts, stream, out, n_targets);
+  if (both) {
+    (void)hipStreamSynchronize(s);  // the build has copied what it needs
+    dmem_free(both);
+  }
+  return rc;
 }
 
 p2p_status p2p_plan_create_grid(const double* xyz, int64_t n, const double* origin, double h, double k,
@@ -275,6 +318,7 @@ p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {
   out->d_mean = plan->B ? (double)plan->n / (double)plan->B : 0.0;
   out->max_sep = plan->max_sep;
   out->n_close_pairs = plan->n_close;
+  out->n_targets = plan->n_targets;
   return P2P_OK;
 }
 
@@ -305,7 +349,8 @@ static p2p_status check_call(p2p_plan plan, int32_t nrhs, p2p_dtype dtype) {
 p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dtype dtype, void* stream) {
   p2p_status rc = check_call(plan, nrhs, dtype);
   if (rc != P2P_OK) return rc;
-  if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
+  if ((plan->n - (plan->distinct_sets ? plan->n_targets : 0) > 0 && !q) || (plan->n_targets > 0 && !y))
+    return fail(P2P_ERR_ARG, "q or y is NULL");
   if (plan->self_batch && nrhs >= kMrhsMin) {
     void* yy = y;
     rc = batch_apply(plan->self_batch, &q, &yy, nrhs, (hipStream_t)stream, plan->timing, plan->timed);
@@ -320,6 +365,7 @@ p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, 
                               int32_t nrhs, p2p_dtype dtype, void* stream) {
   p2p_status rc = check_call(plan, nrhs, dtype);
   if (rc != P2P_OK) return rc;
+  if (plan->distinct_sets) return fail(P2P_ERR_ARG, "no reverse pass for plans of distinct target and source sets");
   if (plan->n > 0 && (!q || !grad_y)) return fail(P2P_ERR_ARG, "q or grad_y is NULL");
   rc = launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
   if (rc == P2P_OK) record_use(plan->last_use, (hipStream_t)stream);

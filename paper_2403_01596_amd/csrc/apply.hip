@@ -82,15 +82,17 @@ __global__ void __launch_bounds__(kBlock) k_apply_cols(SweepGeom<Tr> G, FwdOp<Tr
   sweep<Tr, FwdOp<Tr, M>, HELM, CSR>(G, op, lds[threadIdx.x / kWave]);
 }
 
-// rows of q (original order) -> rows of qs (sorted order)
+// rows of q (original order) -> rows of qs (sorted order).  Plans of distinct sets:
+// q holds the sources only (points n_targets on), and targets' rows are zero.
 template <typename C>
 __global__ void __launch_bounds__(kBlock) k_gather_rows(const C* __restrict__ q, const int32_t* __restrict__ perm,
-                                                     int64_t n, int m, C* __restrict__ qs) {
+                                                     int64_t n, int m, int64_t n_targets, C* __restrict__ qs) {
   int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n * m) return;
   int64_t p = e / m;
   int c = (int)(e - p * m);
-  qs[e] = q[(int64_t)perm[p] * m + c];
+  const int64_t row = (int64_t)perm[p] - n_targets;
+  qs[e] = row >= 0 ? q[row * m + c] : C{};
 }
 
 // 1 / (4 pi) times the unit conversion of the accumulated terms (FP32: quanta)
@@ -113,7 +115,7 @@ static p2p_status run_apply(p2p_plan_s* P, const void* q, void* y, int m, hipStr
   using real = typename Tr::real;
   const int64_t n = P->n;
   hipLaunchKernelGGL(k_gather_rows<cplx>, dim3(grid_for(n * m)), dim3(kBlock), 0, s, (const cplx*)q, P->perm, n, m,
-                     (cplx*)P->q_sorted);
+                     P->distinct_sets ? P->n_targets : (int64_t)0, (cplx*)P->q_sorted);
   SweepGeom<Tr> G = make_geom<Tr>(P);
   const bool helm = P->k != 0.0, csr = P->layout == P2P_LAYOUT_CSR;
   auto kern = helm ? (csr ? k_apply<Tr, true, true> : k_apply<Tr, true, false>)

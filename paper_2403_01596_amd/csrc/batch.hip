@@ -54,6 +54,7 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
   for (int i = 0; i < count; ++i) {
     const p2p_plan_s* P = plans[i];
     if (!P || P->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle in batch");
+    if (P->distinct_sets) return fail(P2P_ERR_ARG, "batches take plans of one point set");
     if (P->precision != P2P_C64) return fail(P2P_ERR_DTYPE, "batches serve complex64 plans");
     if (P->layout != plans[0]->layout) return fail(P2P_ERR_ARG, "all plans of a batch need one layout");
     if (P->max_rhs < m) return fail(P2P_ERR_ARG, "a plan's max_rhs is below nrhs");

@@ -83,6 +83,12 @@ struct p2p_plan_s {
   // than kCloseQuanta quanta; the kernels take those pairs' differences from the
   // FP64 coordinates.
   int32_t* near;       // [B]
+  // Plans of distinct target and source sets: the plan's points are the targets
+  // [0, n_targets) followed by the sources; each box lists its targets first, and
+  // its sources start at src_start[T].  Null for one set.
+  bool distinct_sets;
+  int64_t n_targets;
+  int32_t* src_start;  // [B + 1]
   int64_t n_close;     // ordered near pairs closer than kCloseQuanta quanta, -1 until counted
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
@@ -96,6 +102,11 @@ struct p2p_plan_s {
 };
 
 namespace p2p {
+
+// Box T's sources are the sorted positions [src_begin[T], box_start[T + 1]) and its
+// targets [box_start[T], tgt_end[T]): all its points for one set.
+inline const int32_t* src_begin(const p2p_plan_s* P) { return P->src_start ? P->src_start : P->box_start; }
+inline const int32_t* tgt_end(const p2p_plan_s* P) { return P->src_start ? P->src_start : P->box_start + 1; }
 
 constexpr uint64_t kPlanMagic = 0x7032705f706c616eull;
 

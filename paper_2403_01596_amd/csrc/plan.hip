@@ -644,6 +644,29 @@ __global__ void __launch_bounds__(kBlock) k_runs_write(const K* __restrict__ key
   }
 }
 
+// Plans of distinct sets: the first source of each box.  A box lists its points
+// in input order, targets (indices below n_targets) first, so its first source is
+// found by binary search over perm.  Entry nbox is n.
+__global__ void __launch_bounds__(kBlock) k_src_start(const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ box_start,
+                                                   const DevStatus* __restrict__ status, int64_t n,
+                                                   int64_t n_targets, int32_t* __restrict__ src_start) {
+  const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int32_t nb = status->nbox;
+  if (T > nb) return;
+  if (T == nb) {
+    src_start[T] = (int32_t)n;
+    return;
+  }
+  int32_t lo = box_start[T], hi = box_start[T + 1];
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (perm[mid] < n_targets) lo = mid + 1;
+    else hi = mid;
+  }
+  src_start[T] = lo;
+}
+
 // One box per half wavefront (grid-stride): sorted FP64 coordinates (SoA), the
 // box's bounding box, the largest occupancy and the largest |coordinate|.
 __global__ void __launch_bounds__(kBlock) k_box_geom(const double* __restrict__ xyz, const int32_t* __restrict__ perm,
@@ -754,7 +777,9 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
                                              const int32_t* __restrict__ nbr_start, int32_t* __restrict__ nbr_idx,
                                              Partial* __restrict__ part, const double* __restrict__ sx64,
                                              int32_t* __restrict__ sx32, int64_t n, int qexp,
-                                             int32_t* __restrict__ near, double reach) {
+                                             int32_t* __restrict__ near, double reach,
+                                             const int32_t* __restrict__ src_begin,
+                                             const int32_t* __restrict__ tgt_end) {
   __shared__ uint64_t ldsl[kWavesPerBlockPlan];
   __shared__ double ldsd[kWavesPerBlockPlan];
   __shared__ uint32_t ldsu[kWavesPerBlockPlan];
@@ -808,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
       double sep = 0.0;
       uint32_t meet = 0;
       if (found) {
-        ns = (uint32_t)(box_start[S + 1] - box_start[S]);
+        ns = (uint32_t)(box_start[S + 1] - src_begin[S]);
         bool inter = S != T;
         for (int a = 0; a < 3; ++a) {
           const double up = bb[6 * (int64_t)S + 3 + a] - bb[6 * (int64_t)T + a];
@@ -823,7 +848,7 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
       sep = half_max(sep);
       meet = half_or(meet);
       if (h == 31 && live) {
-        const int32_t nT = box_start[T + 1] - box_start[T];
+        const int32_t nT = tgt_end[T] - box_start[T];
         cnt[T] = (int32_t)c;
         src[T] = (int32_t)ns;
         srcsum += ns;
@@ -895,6 +920,7 @@ __global__ void __launch_bounds__(kBlock) k_own_close(const int32_t* __restrict_
 // neighbourhood into the box's contiguous list, its own points first.
 template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict__ box_start,
+                                                   const int32_t* __restrict__ src_begin,
                                                    const int32_t* __restrict__ nbr_start,
                                                    const int32_t* __restrict__ nbr_idx,
                                                    const int32_t* __restrict__ tile_start, int32_t nb, int64_t n,
@@ -909,7 +935,7 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
   for (int32_t e = nbr_start[T] - 1; e < nbr_start[T + 1]; ++e) {
     const int32_t S = e < nbr_start[T] ? T : nbr_idx[e];
     if (e >= nbr_start[T] && S == T) continue;
-    const int32_t p0 = box_start[S], ns = box_start[S + 1] - p0;
+    const int32_t p0 = src_begin[S], ns = box_start[S + 1] - p0;
     for (int32_t j = lane; j < ns; j += kWave) {
       const int64_t p = p0 + j, d = o + j;
       tsrc[d] = (int32_t)p;
@@ -930,12 +956,13 @@ __global__ void __launch_bounds__(kBlock) k_tile_fill(const int32_t* __restrict_
 // Processing order of the sweep: boxes in decreasing order of their pair slots,
 // bucketed on a log scale (8 buckets per octave), Morton order inside a bucket.
 __global__ void __launch_bounds__(kBlock) k_cost_keys(const int32_t* __restrict__ box_start,
+                                                   const int32_t* __restrict__ tgt_end,
                                                    const int32_t* __restrict__ src,
                                                    const DevStatus* __restrict__ status,
                                                    uint64_t* __restrict__ key) {
   const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (T >= status->nbox) return;
-  const double c = (double)(box_start[T + 1] - box_start[T]) * (double)src[T];
+  const double c = (double)(tgt_end[T] - box_start[T]) * (double)src[T];
   const int b = (int)fmin(255.0, floor(log2(c + 1.0) * 8.0));
   key[T] = (uint64_t)(255 - b);
 }
@@ -954,6 +981,8 @@ __device__ __forceinline__ double lane_read(double v, int j) {
 // compared.
 __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict__ sx, int64_t n,
                                                     const int32_t* __restrict__ box_start,
+                                                    const int32_t* __restrict__ src_begin,
+                                                    const int32_t* __restrict__ tgt_end,
                                                     const int32_t* __restrict__ nbr_start,
                                                     const int32_t* __restrict__ nbr_idx, int32_t nb, bool self_only,
                                                     uint64_t* __restrict__ part) {
@@ -966,7 +995,7 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
     // each; the targets are walked with lane reads, so the inner loop touches no
     // memory.  Lanes past a chunk's end hold NaN, which equals nothing.
     const int32_t e0 = self_only ? 0 : nbr_start[T], e1 = self_only ? 1 : nbr_start[T + 1];
-    const int32_t b0 = box_start[T], b1 = box_start[T + 1];
+    const int32_t b0 = box_start[T], b1 = tgt_end[T];
     for (int32_t tb = b0; tb < b1; tb += kWave) {
       const int nt = min(kWave, b1 - tb);
       const bool tl = lane < nt;
@@ -974,7 +1003,7 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
                    tz = tl ? sx[2 * n + tb + lane] : NAN;
       for (int32_t e = e0; e < e1; ++e) {
         const int32_t S = self_only ? (int32_t)T : nbr_idx[e];
-        const int32_t s0 = box_start[S], s1 = box_start[S + 1];
+        const int32_t s0 = src_begin[S], s1 = box_start[S + 1];
         for (int32_t sb = s0; sb < s1; sb += kWave) {
           const bool sl = lane < s1 - sb;
           const double qx = sl ? sx[sb + lane] : NAN, qy = sl ? sx[n + sb + lane] : NAN,
@@ -997,6 +1026,8 @@ __global__ void __launch_bounds__(kBlock) k_count_zero(const double* __restrict_
 __global__ void __launch_bounds__(kBlock) k_count_close(const int32_t* __restrict__ sx32,
                                                      const double* __restrict__ sx, int64_t n,
                                                      const int32_t* __restrict__ box_start,
+                                                     const int32_t* __restrict__ src_begin,
+                                                     const int32_t* __restrict__ tgt_end,
                                                      const int32_t* __restrict__ nbr_start,
                                                      const int32_t* __restrict__ nbr_idx,
                                                      const int32_t* __restrict__ near, int32_t nb,
@@ -1009,7 +1040,7 @@ __global__ void __launch_bounds__(kBlock) k_count_close(const int32_t* __restric
   if (T < nb) {
     const bool all = near[T] != 0;
     const int32_t e0 = all ? nbr_start[T] : 0, e1 = all ? nbr_start[T + 1] : 1;
-    const int32_t b0 = box_start[T], b1 = box_start[T + 1];
+    const int32_t b0 = box_start[T], b1 = tgt_end[T];
     for (int32_t tb = b0; tb < b1; tb += kWave) {
       const int nt = min(kWave, b1 - tb);
       const int32_t ti = tb + min(lane, nt - 1);
@@ -1017,7 +1048,7 @@ __global__ void __launch_bounds__(kBlock) k_count_close(const int32_t* __restric
       const double fx = sx[ti], fy = sx[n + ti], fz = sx[2 * n + ti];
       for (int32_t e = e0; e < e1; ++e) {
         const int32_t S = all ? nbr_idx[e] : (int32_t)T;
-        const int32_t s0 = box_start[S], s1 = box_start[S + 1];
+        const int32_t s0 = src_begin[S], s1 = box_start[S + 1];
         for (int32_t sb = s0; sb < s1; sb += kWave) {
           const bool sl = lane < s1 - sb;
           const int32_t si = sl ? sb + lane : s0;
@@ -1355,6 +1386,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     P->work = b.take<int32_t>(n);
     P->sx64 = b.take<double>(3 * n);
     P->sx32 = f64 ? nullptr : b.take<int32_t>(3 * n);
+    P->src_start = P->distinct_sets ? b.take<int32_t>(n + 1) : nullptr;
     P->q_sorted = b.take<char>((int64_t)(n * (int64_t)P->max_rhs * cbytes));
     P->g_sorted = b.take<char>((int64_t)(n * (int64_t)P->max_rhs * cbytes));
   };
@@ -1502,6 +1534,9 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
                          P->box_start, status, grid);
     P2P_HIP(hipGetLastError());
   }
+  if (P->src_start)
+    hipLaunchKernelGGL(k_src_start, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, P->perm, P->box_start, status, n,
+                       P->n_targets, P->src_start);
   const unsigned gs = (unsigned)std::min<int64_t>(kGridStride, grid_for(n, kWavesPerBlockPlan));
   hipLaunchKernelGGL(k_box_geom, dim3(gs), dim3(kBlock), 0, s, xyz, P->perm, n, P->box_start, status, P->sx64, bb,
                      part);
@@ -1510,7 +1545,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   //         The counting pass also zeroes entry B, so scanning B + 1 entries gives
   //         the offsets of the B boxes and, at index B, the totals.
   hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
-                     nullptr, nullptr, part, nullptr, nullptr, n, 0, nullptr, 0.0);
+                     nullptr, nullptr, part, nullptr, nullptr, n, 0, nullptr, 0.0, src_begin(P), tgt_end(P));
   hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
   P2P_HIP(hipGetLastError());
   {  // both box-indexed arrays in one set of launches (partu is free once the sort is done)
@@ -1528,7 +1563,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     StatusCopy copy;
     rc = copy.start(status, s);
     if (rc != P2P_OK) return rc;
-    hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, P->box_start, src, status, k0);
+    hipLaunchKernelGGL(k_cost_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, P->box_start, tgt_end(P), src, status, k0);
     P2P_HIP(hipGetLastError());
     rc = radix_sort(k0, P->work, k1, v1, n, 8, hist, partu, &sk, s, &status->nbox);
     if (rc != P2P_OK) return rc;
@@ -1586,17 +1621,20 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   const double reach = std::ldexp((double)kCloseQuanta + 2.0, P->qexp);
   hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
                      dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
-                     P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp, P->near, reach);
+                     P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp, P->near, reach, src_begin(P),
+                     tgt_end(P));
   if (!f64)
     hipLaunchKernelGGL(k_own_close, dim3(grid_for(B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx32, n,
                        P->box_start, B, P->near);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)
-      hipLaunchKernelGGL(k_tile_fill<true>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
+      hipLaunchKernelGGL(k_tile_fill<true>, dim3(g), dim3(kBlock), 0, s, P->box_start, src_begin(P), P->nbr_start,
+                         P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
     else
-      hipLaunchKernelGGL(k_tile_fill<false>, dim3(g), dim3(kBlock), 0, s, P->box_start, P->nbr_start, P->nbr_idx,
+      hipLaunchKernelGGL(k_tile_fill<false>, dim3(g), dim3(kBlock), 0, s, P->box_start, src_begin(P), P->nbr_start,
+                         P->nbr_idx,
                          P->tile_start, B, n, P->tile_len, P->sx64, P->sx32, P->tile_src, P->tile_x64, P->tile_x32);
   }
   P2P_HIP(hipGetLastError());
@@ -1614,12 +1652,13 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(1), dim3(kBlock), 0, s, (uint32_t*)status,
                      (int64_t)(sizeof(DevStatus) / sizeof(uint32_t)), nullptr, nullptr, (int64_t)0, nullptr, (int64_t)0);
   if (P->B > 0) {
-    hipLaunchKernelGGL(k_count_zero, dim3(g), dim3(kBlock), 0, s, P->sx64, P->n, P->box_start, P->nbr_start,
+    hipLaunchKernelGGL(k_count_zero, dim3(g), dim3(kBlock), 0, s, P->sx64, P->n, P->box_start, src_begin(P),
+                       tgt_end(P), P->nbr_start,
                        P->nbr_idx, (int32_t)P->B, !P->may_coincide, part);
     hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->zero);
     if (P->near) {
       hipLaunchKernelGGL(k_count_close, dim3(g), dim3(kBlock), 0, s, P->sx32, P->sx64, P->n, P->box_start,
-                         P->nbr_start, P->nbr_idx, P->near, (int32_t)P->B, part);
+                         src_begin(P), tgt_end(P), P->nbr_start, P->nbr_idx, P->near, (int32_t)P->B, part);
       hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->ncp);
     }
   }

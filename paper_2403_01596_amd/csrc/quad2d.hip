@@ -435,6 +435,7 @@ p2p_status p2p2d_destroy(p2p2d h) {
 p2p_status p2p_apply_log2d(p2p_plan plan, const double* q, double* y, void* stream) {
   if (!plan || !handle_live(plan) || plan->magic != kPlanMagic) return fail(P2P_ERR_STATE, "invalid plan handle");
   if (plan->precision != P2P_C128) return fail(P2P_ERR_DTYPE, "the 2-D kernel runs on FP64 (complex128) plans");
+  if (plan->distinct_sets) return fail(P2P_ERR_ARG, "the 2-D kernel runs on plans of one point set");
   if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
   if (plan->n == 0) return P2P_OK;
   const hipStream_t s = (hipStream_t)stream;

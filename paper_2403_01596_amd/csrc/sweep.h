@@ -226,6 +226,13 @@ struct SweepGeom {
   const int32_t* work;
   int32_t nb;
   const int32_t* box_start;
+  // Box T's targets are the sorted positions [box_start[T], tgt_end[T]), its sources
+  // [src_begin[T], box_start[T + 1]).  One point set: both are all its points
+  // (src_begin = box_start, tgt_end = box_start + 1).  Distinct sets (st): targets
+  // first, then sources, and no target is also a source.
+  const int32_t* src_begin;
+  const int32_t* tgt_end;
+  bool st;
   const int32_t* tile_start;
   const int32_t* tsrc;
   const typename Tr::coord* tx;  // [3][tl]
@@ -252,6 +259,9 @@ inline SweepGeom<Tr> make_geom(const p2p_plan_s* P) {
   G.work = P->work;
   G.nb = (int32_t)P->B;
   G.box_start = P->box_start;
+  G.src_begin = src_begin(P);
+  G.tgt_end = tgt_end(P);
+  G.st = P->src_start != nullptr;
   G.tile_start = P->tile_start;
   G.tsrc = P->tile_src;
   G.tl = P->tile_len;
@@ -283,9 +293,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Sorted positions of neighbourhood entries [sg, sg + cap) of box T, into idx.  The
-// neighbourhood is ordered as the replicated lists are: the box's own points first,
-// then the other neighbour boxes in list order.
+// neighbourhood is ordered as the replicated lists are: the box's own sources first,
+// then the other neighbour boxes' in list order; box S's sources are the sorted
+// positions [src_begin[S], box_start[S + 1]).
 __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, const int32_t* __restrict__ box_start,
+                                            const int32_t* __restrict__ src_begin,
                                             const int32_t* __restrict__ nbr_start,
                                             const int32_t* __restrict__ nbr_idx, int32_t* idx, int lane) {
   int32_t off = 0;
@@ -293,7 +305,7 @@ __device__ __forceinline__ void csr_indices(int32_t T, int32_t sg, int32_t cap, 
   for (int32_t j = j0 - 1; j < j1; ++j) {
     const int32_t S = j < j0 ? T : ld_uniform(nbr_idx + j);
     if (j >= j0 && S == T) continue;
-    const int32_t a = ld_uniform(box_start + S), len = ld_uniform(box_start + S + 1) - a;
+    const int32_t a = ld_uniform(src_begin + S), len = ld_uniform(box_start + S + 1) - a;
     const int32_t lo = max(off, sg), hi = min(off + len, sg + cap);
     for (int32_t e = lo + lane; e < hi; e += kWave) idx[e - sg] = a + (e - off);
     off += len;
@@ -323,6 +335,8 @@ enum SweepMask { kMaskAll, kMaskFirst, kMaskNone };
 // and the source (entry of the group) of one close pair.
 __device__ __forceinline__ int32_t close_entry(int32_t t_off, int32_t e_off) { return (t_off << 16) | e_off; }
 constexpr int32_t kNoMiss = 0x7fffffff;
+// self_off of plans whose targets are not sources: no entry is a target's own
+constexpr int32_t kNoSelf = -(1 << 30);
 
 // The close pairs of target t in chunk c of a group: lanes whose fixed-point r2 is
 // at most kCloseR2 (so that the FP32 geometry gave them no term; far: the others),
@@ -503,13 +517,16 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
   const int32_t w = uniform((int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
   if (w >= G.nb) return;
   const int32_t T = ld_uniform(G.work + w);
-  const int32_t t0 = ld_uniform(G.box_start + T), t1 = ld_uniform(G.box_start + T + 1);
+  const int32_t t0 = ld_uniform(G.box_start + T), t1 = ld_uniform(G.tgt_end + T);
+  // the box's own sources, first in its neighbourhood list; a target's own entry
+  // (its self pair) is entry t + so of the list, with one point set only
+  const int32_t n_own = ld_uniform(G.box_start + T + 1) - ld_uniform(G.src_begin + T);
   int32_t s0 = 0, s1 = 0;
   if (CSR) {
     const int32_t j1 = ld_uniform(G.nbr_start + T + 1);
     for (int32_t j = ld_uniform(G.nbr_start + T); j < j1; ++j) {
       const int32_t S = ld_uniform(G.nbr_idx + j);
-      s1 += ld_uniform(G.box_start + S + 1) - ld_uniform(G.box_start + S);
+      s1 += ld_uniform(G.box_start + S + 1) - ld_uniform(G.src_begin + S);
     }
   } else {
     s0 = ld_uniform(G.tile_start + T);
@@ -519,18 +536,25 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
   const bool near_box = G.near != nullptr && ld_uniform(G.near + T) != 0;
   for (int32_t tb = t0; tb < t1; tb += kWave) {
     const int32_t te = min(tb + kWave, t1);
+    if (s1 == s0) {  // no sources near the box (distinct sets only): zero sums
+      real zero[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) zero[a] = real(0);
+      if (tb + lane < te) op.store(tb + lane, zero);
+      continue;
+    }
     for (int32_t sg = s0; sg < s1; sg += kWave * K) {
       const int nch = min(K, (s1 - sg + kWave - 1) / kWave);
-      if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.nbr_start, G.nbr_idx, L.idx, lane);
+      if (CSR) csr_indices(T, sg, kWave * K, G.box_start, G.src_begin, G.nbr_start, G.nbr_idx, L.idx, lane);
       const bool first_group = sg == s0;
       // A zero distance can only occur among the box's own points, entries
       // [s0, s0 + n_T), unless points of distinct boxes may coincide; a close pair
       // (FP32) only in a box marked near, whose chunks all take the masked form
       // with the close-pair test.  Padding entries sit far away.  The first-chunk
       // form needs all own points in the first chunk of the first group.
-      const bool own_here = sg < s0 + (t1 - t0);
-      const int32_t so = s0 - t0;
-      const int mode = (G.may_coincide || (own_here && !(first_group && t1 - t0 <= kWave)))
+      const bool own_here = sg < s0 + n_own;
+      const int32_t so = G.st ? kNoSelf : s0 - t0;
+      const int mode = (G.may_coincide || (own_here && !(first_group && n_own <= kWave)))
                            ? kMaskAll
                            : (first_group ? kMaskFirst : kMaskNone);
       coord X[K], Y[K], Z[K];
