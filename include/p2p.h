@@ -25,8 +25,13 @@
  *  - The caller owns every array it passes.  A plan owns the device memory it
  *    allocates and frees it in p2p_plan_destroy.
  *  - stream is a hipStream_t (NULL: the legacy default stream).  Work is
- *    enqueued on it.  p2p_plan_create waits for its own work before returning;
- *    the other calls return as soon as their work is enqueued.
+ *    enqueued on it, and calls return as soon as their work is enqueued.  The
+ *    p2p_plan_create calls wait on the host only for two small readbacks of
+ *    their own work, mid-build; the rest of the build may still be running when
+ *    they return.  Later calls on the build's stream are ordered after it by the
+ *    stream; the first call on any other stream (and every call that reads the
+ *    plan on the host: p2p_plan_info, p2p_plan_export, p2p_batch_create) waits
+ *    for the build on the host first.
  *  - A call returns a status and never aborts.  On error no output is written
  *    (for asynchronous calls: no work is enqueued) and p2p_last_error() returns
  *    a message for the calling thread.
@@ -176,7 +181,8 @@ p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out);
  * Morton order with their points, and each box's neighbour boxes (paper section
  * 3.2: targets and neighbour sources of every box, with their offset arrays):
  * box_key u64[B], box_start i32[B+1], perm i32[n] (sorted position -> original
- * index), nbr_start i32[B+1], nbr_idx i32[n_nbr].  Synchronous. */
+ * index), nbr_start i32[B+1], nbr_idx i32[n_nbr].  Synchronous: waits for the
+ * plan's build, not for other work on the device. */
 p2p_status p2p_plan_export(p2p_plan plan, uint64_t* box_key, int32_t* box_start, int32_t* perm, int32_t* nbr_start,
                            int32_t* nbr_idx);
 
@@ -248,10 +254,11 @@ p2p_status p2p_batch_timing_read(p2p_batch batch, double* ms, int64_t* calls);
  * P2P_ERR_STATE and is not read. */
 p2p_status p2p_batch_destroy(p2p_batch batch);
 
-/* Frees the plan.  Waits first for the work of the plan's last p2p_apply or
- * p2p_apply_backward call outside graph capture (calls on one plan are ordered,
- * so this covers every earlier one); graphs that captured the plan's work must
- * not be replayed after this.  NULL is a no-op; a handle that is not a live plan
+/* Frees the plan without waiting: its device memory goes back to the library's
+ * cache, to be handed out again only once the plan's build and its last
+ * p2p_apply or p2p_apply_backward call outside graph capture have completed on
+ * the device (calls on one plan are ordered, so that covers every earlier one);
+ * graphs that captured the plan's work must not be replayed after this.  NULL is a no-op; a handle that is not a live plan
  * (destroyed already, or never created) gives P2P_ERR_STATE and is not read.
  * Plan creation fails with P2P_ERR_NOMEM when device memory runs out; the
  * environment variable P2P_TEST_FAIL_ALLOC=n makes the library's n-th device

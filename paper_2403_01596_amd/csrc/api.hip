@@ -45,14 +45,26 @@ bool handle_live(const void* h) {
   return g_handles && g_handles->count(h) != 0;
 }
 
-void record_use(hipEvent_t ev, hipStream_t s) {
-  if (!ev) return;
+bool record_use(hipEvent_t ev, hipStream_t s) {
+  if (!ev) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
     (void)hipGetLastError();
-    return;
+    return false;
   }
-  if (cs == hipStreamCaptureStatusNone) (void)hipEventRecord(ev, s);
+  if (cs != hipStreamCaptureStatusNone) return false;
+  if (hipEventRecord(ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+p2p_status wait_built(p2p_plan_s* P, hipStream_t s, bool force) {
+  if (P->built || !P->ready || (!force && s == P->build_stream)) return P2P_OK;
+  P2P_HIP(hipEventSynchronize(P->ready));
+  P->built = true;
+  return P2P_OK;
 }
 
 static p2p_status check_plan(p2p_plan_s* P) {
@@ -87,23 +99,24 @@ static void drop_events(p2p_plan_s* P) {
   P->timed->clear();
 }
 
-// Waits for the plan's last recorded work (its calls are ordered, so that covers
-// every earlier one), then releases everything.
+// Releases everything.  The device memory goes back to the cache behind the
+// plan's last recorded work (the build, or its last call: calls on a plan are
+// ordered, so that covers every earlier one), without a host wait.
 static p2p_status free_plan(p2p_plan_s* P) {
   p2p_status rc = P2P_OK;
   handle_remove(P);
   int cur = P->device;
   (void)hipGetDevice(&cur);
   if (cur != P->device) (void)hipSetDevice(P->device);
-  if (P->last_use) {
-    if (hipEventSynchronize(P->last_use) != hipSuccess) rc = fail(P2P_ERR_HIP, "hipEventSynchronize failed in destroy");
-    (void)hipEventDestroy(P->last_use);
-  }
   if (P->self_batch) batch_free(P->self_batch);
   drop_events(P);
   delete P->timed;
-  dmem_free(P->arena);
-  dmem_free(P->arena2);
+  // the event recorded last (the last call's, or the build's) goes to the cache,
+  // which owns it from here
+  hipEvent_t rel = P->used ? P->last_use : P->ready, other = P->used ? P->ready : P->last_use;
+  void* blocks[2] = {P->arena, P->arena2};
+  dmem_free_after(blocks, 2, rel);
+  if (other) (void)hipEventDestroy(other);
   if (cur != P->device) (void)hipSetDevice(cur);
   P->magic = 0;
   delete P;
@@ -210,13 +223,29 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   }
   handle_add(P);
   p2p_status rc = P2P_OK;
-  if (hipEventCreateWithFlags(&P->last_use, hipEventDisableTiming) != hipSuccess) {
-    P->last_use = nullptr;
+  const hipStream_t s = (hipStream_t)stream;
+  P->build_stream = s;
+  if (hipEventCreateWithFlags(&P->last_use, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ready, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
     rc = fail(P2P_ERR_HIP, "hipEventCreateWithFlags failed");
   }
-  if (rc == P2P_OK) rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, (hipStream_t)stream);
+  if (rc == P2P_OK) {
+    rc = build_plan(P, xyz, box_ijk, box_ijk ? nullptr : gspec, s);
+    // the build returns once its work is enqueued: the event marks its end, for
+    // calls on other streams and, until the plan is used, for the release of its
+    // memory
+    if (hipEventRecord(P->ready, s) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);
+      P->built = true;
+      (void)hipEventDestroy(P->ready);
+      P->ready = nullptr;
+    }
+  }
   if (rc == P2P_OK && P->precision == P2P_C64 && P->max_rhs >= kMrhsMin && !P->distinct_sets) {
-    rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
+    rc = wait_built(P, nullptr, true);  // the batch tables are made from the plan's arrays on the host
+    if (rc == P2P_OK) rc = batch_create(&P, 1, P->max_rhs, &P->self_batch);
     if (rc == P2P_OK && o.tune_cache) batch_use_cache(P->self_batch, o.tune_cache);
   }
   if (rc != P2P_OK) {
@@ -273,10 +302,7 @@ p2p_status p2p_plan_create_st(const double* targets, int64_t n_targets, const do
   }
   const p2p::GridSpec g{{origin[0], origin[1], origin[2]}, h};
   const p2p_status rc = create_plan((const double*)both, nullptr, &g, n, k, opts, stream, out, n_targets);
-  if (both) {
-    (void)hipStreamSynchronize(s);  // the build has copied what it needs
-    dmem_free(both);
-  }
+  dmem_free_on(&both, 1, s);  // behind the build, which has copied what it needs
   return rc;
 }
 
@@ -303,7 +329,8 @@ p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {
   p2p_status rc = check_plan(plan);
   if (rc != P2P_OK) return rc;
   if (!out) return fail(P2P_ERR_ARG, "out is NULL");
-  rc = count_pairs(plan, nullptr);
+  rc = wait_built(plan, nullptr, true);
+  if (rc == P2P_OK) rc = count_pairs(plan, nullptr);
   if (rc != P2P_OK) return rc;
   out->n_points = plan->n;
   out->n_boxes = plan->B;
@@ -327,7 +354,8 @@ p2p_status p2p_plan_export(p2p_plan plan, uint64_t* box_key, int32_t* box_start,
   p2p_status rc = check_plan(plan);
   if (rc != P2P_OK) return rc;
   const int64_t B = plan->B, n = plan->n;
-  P2P_HIP(hipDeviceSynchronize());
+  rc = wait_built(plan, nullptr, true);
+  if (rc != P2P_OK) return rc;
   if (box_key && B) P2P_HIP(hipMemcpy(box_key, plan->box_key, sizeof(uint64_t) * B, hipMemcpyDeviceToHost));
   if (box_start) P2P_HIP(hipMemcpy(box_start, plan->box_start, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost));
   if (perm && n) P2P_HIP(hipMemcpy(perm, plan->perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
@@ -351,13 +379,15 @@ p2p_status p2p_apply(p2p_plan plan, const void* q, void* y, int32_t nrhs, p2p_dt
   if (rc != P2P_OK) return rc;
   if ((plan->n - (plan->distinct_sets ? plan->n_targets : 0) > 0 && !q) || (plan->n_targets > 0 && !y))
     return fail(P2P_ERR_ARG, "q or y is NULL");
+  rc = wait_built(plan, (hipStream_t)stream);
+  if (rc != P2P_OK) return rc;
   if (plan->self_batch && nrhs >= kMrhsMin) {
     void* yy = y;
     rc = batch_apply(plan->self_batch, &q, &yy, nrhs, (hipStream_t)stream, plan->timing, plan->timed);
   } else {
     rc = launch_apply(plan, q, y, nrhs, (hipStream_t)stream);
   }
-  if (rc == P2P_OK) record_use(plan->last_use, (hipStream_t)stream);
+  if (rc == P2P_OK && record_use(plan->last_use, (hipStream_t)stream)) plan->used = true;
   return rc;
 }
 
@@ -367,8 +397,10 @@ p2p_status p2p_apply_backward(p2p_plan plan, const void* q, const void* grad_y, 
   if (rc != P2P_OK) return rc;
   if (plan->distinct_sets) return fail(P2P_ERR_ARG, "no reverse pass for plans of distinct target and source sets");
   if (plan->n > 0 && (!q || !grad_y)) return fail(P2P_ERR_ARG, "q or grad_y is NULL");
+  rc = wait_built(plan, (hipStream_t)stream);
+  if (rc != P2P_OK) return rc;
   rc = launch_backward(plan, q, grad_y, grad_q, grad_xyz, nrhs, (hipStream_t)stream);
-  if (rc == P2P_OK) record_use(plan->last_use, (hipStream_t)stream);
+  if (rc == P2P_OK && record_use(plan->last_use, (hipStream_t)stream)) plan->used = true;
   return rc;
 }
 

@@ -60,6 +60,10 @@ p2p_status batch_create(p2p_plan_s* const* plans, int count, int m, p2p_batch_s*
     if (P->max_rhs < m) return fail(P2P_ERR_ARG, "a plan's max_rhs is below nrhs");
     if (P->device != plans[0]->device) return fail(P2P_ERR_ARG, "all plans of a batch need one device");
   }
+  for (int i = 0; i < count; ++i) {  // the tables below are made from the plans' arrays on the host
+    const p2p_status rc = wait_built(plans[i], nullptr, true);
+    if (rc != P2P_OK) return rc;
+  }
   p2p_batch_s* b = new (std::nothrow) p2p_batch_s();
   if (!b) return fail(P2P_ERR_NOMEM, "host allocation failed");
   b->magic = kBatchMagic;

@@ -95,7 +95,11 @@ struct p2p_plan_s {
   void* g_sorted;      // [n * max_rhs] complex
   // complex64 plans with max_rhs >= 16: the matrix-core path for many right-hand sides
   p2p_batch_s* self_batch;
-  hipEvent_t last_use;  // recorded after each call's work: destroy waits for it
+  hipEvent_t last_use;  // recorded after each call's work (used: at least once)
+  hipEvent_t ready;     // recorded after the build
+  hipStream_t build_stream;
+  bool built;           // the build is known to be complete
+  bool used;            // destroy releases the plan's memory behind last_use, else ready
   // diagnostics: event pairs around the sweep kernels
   bool timing;
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* timed;
@@ -120,13 +124,25 @@ bool handle_live(const void* h);
 // Records ev on stream s unless s is being captured into a graph (a recorded
 // event there would only be reached by replays): the last call a destroy has to
 // wait for.
-void record_use(hipEvent_t ev, hipStream_t s);
+bool record_use(hipEvent_t ev, hipStream_t s);  // true: recorded
+
+// Before work on plan P that runs on stream s: when s is not the stream the plan
+// was built on, waits for the build on the host (once; later calls find it
+// complete).  Host reads of the plan's arrays pass s = nullptr with force.
+p2p_status wait_built(p2p_plan_s* P, hipStream_t s, bool force = false);
 
 // device memory cache and pinned staging (memory.hip)
 // P2P_TEST_FAIL_ALLOC=n (test hook): the n-th allocation after the variable is set
 // (or changed) fails as if the device were out of memory.
 void* dmem_alloc(size_t bytes);  // current device; nullptr when out of memory
 void dmem_free(void* p);         // the caller guarantees no pending work uses p
+// Stream-ordered releases (no host wait): the blocks are handed out again once the
+// work before event ev has completed; the cache takes ownership of ev (null: no
+// pending work, released at once).  At most two blocks per call.
+void dmem_free_after(void* const* blocks, int count, hipEvent_t ev);
+// The blocks (at most two; null entries skipped) are handed out again once the
+// work enqueued on s so far has completed: one event for all of them.
+void dmem_free_on(void* const* blocks, int count, hipStream_t s);
 struct StagingLock {
   void* host = nullptr;  // pinned host buffer, valid while the lock is held
   std::unique_lock<std::mutex> lock;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -763,12 +764,40 @@ __device__ __forceinline__ int32_t fixed_point(double x, int qexp) {
   return (int32_t)(uint32_t)(uint64_t)(int64_t)v;
 }
 
+// Lane l of each 32-lane half reads lane l ^ J of the same half (swizzle, bit-mask
+// mode: and-mask 31, xor-mask J).  (DPP row rotations would spare the LDS
+// crossbar, but folded by the compiler into the integer subtraction that uses
+// them they were measured on gfx950 to read the lane's own value, and kept as
+// moves of their own they cost more instructions than the swizzles.)
+template <int J>
+__device__ __forceinline__ uint32_t swizzle_xor(int32_t v) {
+  return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1f | (J << 10));
+}
+
+// Whether lane h's point (u = its fixed-point coordinates plus kCloseQuanta) lies
+// within kCloseQuanta quanta, on every axis, of the point y held by lane h ^ J of
+// its half, for one of the partners J = OFF + j; lanes h ^ J at or beyond ns hold
+// no point.  All lanes take part in every swizzle (no short-circuit).
+template <int OFF, int... j>
+__device__ __forceinline__ bool close_partners(const uint32_t (&u)[3], const int32_t (&y)[3], int h, int32_t ns,
+                                               std::integer_sequence<int, j...>) {
+  constexpr uint32_t kTwoQ = 2u * (uint32_t)kCloseQuanta;
+  bool hit = false;
+  ((hit = hit | (((h ^ (OFF + j)) < ns) &
+                 (max(max(u[0] - swizzle_xor<OFF + j>(y[0]), u[1] - swizzle_xor<OFF + j>(y[1])),
+                      u[2] - swizzle_xor<OFF + j>(y[2])) <= kTwoQ))),
+   ...);
+  return hit;
+}
+
 // FILL false: neighbour counts, neighbourhood sizes and the geometry bounds.  FILL
 // true: the lists themselves and, when sx32 is given (FP32 plans), the fixed-point
-// coordinates of the box's own points and the box's near flag: whether the
+// coordinates of the box's own points and the box's near flag: whether two of its
+// own points lie within kCloseQuanta quanta of each other on every axis, or the
 // bounding box of another neighbour comes within reach of the box's own on every
-// axis.  Each half of a wavefront takes one box (27 of its 32 lanes look up the
-// neighbours), so a wavefront has two boxes' lookups in flight.
+// axis; either way every pair whose fixed-point r2 is at most kCloseR2 lies in a
+// box marked near.  Each half of a wavefront takes one box (27 of its 32 lanes
+// look up the neighbours), so a wavefront has two boxes' lookups in flight.
 template <bool FILL>
 __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box_key,
                                              const int32_t* __restrict__ box_start, const double* __restrict__ bb,
@@ -810,12 +839,35 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
       }
       if (found) nbr_idx[nbr_start[T] + rank] = S;
       if (sx32) {
-        if (live) {
-          const int32_t p1 = box_start[T + 1];
-          for (int32_t p = box_start[T] + h; p < p1; p += 32)
-            for (int d = 0; d < 3; ++d) sx32[d * n + p] = fixed_point(sx64[d * n + p], qexp);
+        // the box's own points in chunks of 32 per half: their fixed-point
+        // coordinates, and whether two of them lie within kCloseQuanta quanta of each
+        // other on every axis (coincident points included), each chunk tested
+        // against itself and against the box's earlier chunks
+        const int32_t b0 = live ? box_start[T] : 0, b1 = live ? box_start[T + 1] : 0;
+        const int32_t nc = (b1 - b0 + 31) >> 5;
+        const int32_t ncw = max(__builtin_amdgcn_readlane(nc, 0), __builtin_amdgcn_readlane(nc, 32));
+        bool own = false;
+        for (int32_t ci = 0; ci < ncw; ++ci) {
+          const int32_t pt = b0 + 32 * ci + h;
+          const bool vt = pt < b1;
+          int32_t X[3] = {0, 0, 0};
+          if (vt)
+            for (int d = 0; d < 3; ++d) {
+              X[d] = fixed_point(sx64[d * n + pt], qexp);
+              sx32[d * n + pt] = X[d];
+            }
+          const uint32_t U[3] = {(uint32_t)X[0] + kCloseQuanta, (uint32_t)X[1] + kCloseQuanta,
+                                 (uint32_t)X[2] + kCloseQuanta};
+          own = own | (vt & close_partners<1>(U, X, h, b1 - b0 - 32 * ci, std::make_integer_sequence<int, 31>{}));
+          for (int32_t cj = 0; cj < ci; ++cj) {
+            const int32_t ps = b0 + 32 * cj + h;
+            int32_t Y[3] = {0, 0, 0};
+            if (ps < b1)
+              for (int d = 0; d < 3; ++d) Y[d] = fixed_point(sx64[d * n + ps], qexp);
+            own = own | (vt & close_partners<0>(U, Y, h, b1 - b0 - 32 * cj, std::make_integer_sequence<int, 32>{}));
+          }
         }
-        uint32_t close = 0;
+        uint32_t close = own ? 1u : 0u;
         if (found && S != T) {
           bool within = true;
           for (int a = 0; a < 3; ++a) {
@@ -823,7 +875,7 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
                                     bb[6 * (int64_t)T + a] - bb[6 * (int64_t)S + 3 + a]);
             within = within && gap < reach;
           }
-          close = within ? 1u : 0u;
+          close |= within ? 1u : 0u;
         }
         close = half_or(close);
         if (h == 31 && live) near[T] = (int32_t)close;
@@ -877,43 +929,6 @@ __global__ void __launch_bounds__(kBlock) k_nbr(const uint64_t* __restrict__ box
       p.overlap = overlap;
     }
   }
-}
-
-// FP32 plans, after k_nbr<true>: marks box T near also when two of its own points
-// lie within kCloseQuanta quanta of each other on every axis (coincident points
-// included), which every pair whose fixed-point r2 is at most kCloseR2 does.  One
-// wavefront per box; targets in lanes, the sources of the same box walked from
-// lane reads, 64 at a time, until one pair is found.
-__global__ void __launch_bounds__(kBlock) k_own_close(const int32_t* __restrict__ sx32, int64_t n,
-                                                   const int32_t* __restrict__ box_start, int32_t nb,
-                                                   int32_t* __restrict__ near) {
-  const int32_t T = uniform((int32_t)(blockIdx.x * kWavesPerBlockPlan + threadIdx.x / kWave));
-  if (T >= nb) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int32_t b0 = box_start[T], b1 = box_start[T + 1];
-  constexpr uint32_t kTwoQ = 2u * (uint32_t)kCloseQuanta;
-  bool found = false;
-  for (int32_t tb = b0; tb < b1 && !found; tb += kWave) {
-    const int32_t ti = min(tb + lane, b1 - 1);
-    // u = x + kCloseQuanta: a source s is within kCloseQuanta on an axis iff
-    // u - s (modulo 2^32) is at most 2 kCloseQuanta
-    const uint32_t ux = (uint32_t)sx32[ti] + kCloseQuanta, uy = (uint32_t)sx32[n + ti] + kCloseQuanta,
-                   uz = (uint32_t)sx32[2 * n + ti] + kCloseQuanta;
-    for (int32_t sb = b0; sb < b1 && !found; sb += kWave) {
-      const int32_t si = min(sb + lane, b1 - 1);
-      const int32_t vx = sx32[si], vy = sx32[n + si], vz = sx32[2 * n + si];
-      const int ns = min(kWave, b1 - sb);
-      bool hit = false;
-      for (int j = 0; j < ns; ++j) {
-        const uint32_t dx = ux - (uint32_t)__builtin_amdgcn_readlane(vx, j);
-        const uint32_t dy = uy - (uint32_t)__builtin_amdgcn_readlane(vy, j);
-        const uint32_t dz = uz - (uint32_t)__builtin_amdgcn_readlane(vz, j);
-        hit = hit || (dx <= kTwoQ && dy <= kTwoQ && dz <= kTwoQ && ti != sb + j);
-      }
-      found = __ballot(hit && tb + lane < b1) != 0;
-    }
-  }
-  if (found && lane == 0) near[T] = 1;
 }
 
 // Replicated source lists: one wavefront per target box copies the points of its
@@ -1131,18 +1146,21 @@ p2p_status dev_alloc(void** p, size_t bytes) {
   return P2P_OK;
 }
 
-// Scratch that goes back to the cache when the scope ends; waits for the stream
-// first so that no enqueued work still reads it.
+// Scratch that goes back to the cache when the scope ends, behind the work
+// enqueued on the stream so far (no host wait).
 struct ScopedBlock {
   void* p = nullptr;
   hipStream_t s;
   explicit ScopedBlock(hipStream_t st) : s(st) {}
-  ~ScopedBlock() {
-    if (p) {
-      (void)hipStreamSynchronize(s);
-      dmem_free(p);
-    }
-  }
+  ~ScopedBlock() { dmem_free_on(&p, 1, s); }
+};
+
+// Two such blocks released behind one event.
+struct ScopedBlocks2 {
+  void* p[2] = {nullptr, nullptr};
+  hipStream_t s;
+  explicit ScopedBlocks2(hipStream_t st) : s(st) {}
+  ~ScopedBlocks2() { dmem_free_on(p, 2, s); }
 };
 
 // Copies the device status block to the host (one copy through pinned memory)
@@ -1423,11 +1441,11 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
     part32 = b.take<int32_t>(scan_parts);
     bb = b.take<double>(6 * std::max<int64_t>(n, 1));
   };
-  ScopedBlock tmp(s), tbl(s);
-  rc = dev_alloc(&tmp.p, measure(carvet));
+  ScopedBlocks2 tmp(s);  // p[0]: this scratch, p[1]: the dense cell table
+  rc = dev_alloc(&tmp.p[0], measure(carvet));
   if (rc != P2P_OK) return rc;
   {
-    Bump b{(char*)tmp.p, 0};
+    Bump b{(char*)tmp.p[0], 0};
     carvet(b);
   }
   // status block and partial rows are contiguous in the scratch block
@@ -1485,9 +1503,9 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
                             (int64_t)hs.st[ST_HI_Z] - lo[2] + 3};
     const double cells = (double)ext[0] * (double)ext[1] * (double)ext[2];
     if (cells <= (double)table_cell_limit(n)) {
-      tbl.p = dmem_alloc(sizeof(int32_t) * (size_t)cells);  // no room: fall back to binary search
-      if (tbl.p) {
-        grid = CellGrid{(int32_t*)tbl.p, lo[0], lo[1], lo[2], ext[0], ext[1]};
+      tmp.p[1] = dmem_alloc(sizeof(int32_t) * (size_t)cells);  // no room: fall back to binary search
+      if (tmp.p[1]) {
+        grid = CellGrid{(int32_t*)tmp.p[1], lo[0], lo[1], lo[2], ext[0], ext[1]};
         table_cells = (int64_t)cells;  // marked empty by the box-table pass
       }
     }
@@ -1619,13 +1637,11 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   // coordinate rounds by at most half a quantum; the bounding boxes' FP64
   // differences by far less than the second quantum of margin)
   const double reach = std::ldexp((double)kCloseQuanta + 2.0, P->qexp);
-  hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)std::min<int64_t>(kGridStride, grid_for(B, kWavesPerBlockPlan))),
+  // the filling pass writes no partial rows: one wavefront per two boxes
+  hipLaunchKernelGGL(k_nbr<true>, dim3((unsigned)grid_for(B, 2 * kWavesPerBlockPlan)),
                      dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src, P->nbr_start,
                      P->nbr_idx, part, P->sx64, f64 ? nullptr : P->sx32, n, P->qexp, P->near, reach, src_begin(P),
                      tgt_end(P));
-  if (!f64)
-    hipLaunchKernelGGL(k_own_close, dim3(grid_for(B, kWavesPerBlockPlan)), dim3(kBlock), 0, s, P->sx32, n,
-                       P->box_start, B, P->near);
   if (tiles) {
     const unsigned g = grid_for(B, kWavesPerBlockPlan);
     if (f64)

@@ -439,6 +439,8 @@ p2p_status p2p_apply_log2d(p2p_plan plan, const double* q, double* y, void* stre
   if (plan->n > 0 && (!q || !y)) return fail(P2P_ERR_ARG, "q or y is NULL");
   if (plan->n == 0) return P2P_OK;
   const hipStream_t s = (hipStream_t)stream;
+  const p2p_status rc = wait_built(plan, s);
+  if (rc != P2P_OK) return rc;
   hipLaunchKernelGGL(k_gather_real, dim3(grid_for(plan->n)), dim3(kBlock), 0, s, q, plan->perm, plan->n,
                      (double*)plan->q_sorted);
   const SweepGeom<L2D> G = make_geom<L2D>(plan);
@@ -451,7 +453,7 @@ p2p_status p2p_apply_log2d(p2p_plan plan, const double* q, double* y, void* stre
     hipLaunchKernelGGL(k_log2d<false>, dim3(grid_for(G.nb, kWavesPerBlock)), dim3(kBlock), 0, s, G, op);
   timer.stop();
   P2P_HIP(hipGetLastError());
-  record_use(plan->last_use, s);
+  if (record_use(plan->last_use, s)) plan->used = true;
   return P2P_OK;
 }
 

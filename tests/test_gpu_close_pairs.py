@@ -261,3 +261,56 @@ def test_matrix_cores_clusters(clusters):
         m, e_abs.max(), rel_l2(y, ref)), flush=True)
     assert e_abs.max() <= ABS_TOL and rel_l2(y, ref) <= 1e-6
     P.close()
+
+
+def lane_pairs(seed=8):
+    """Isolated boxes (ids three apart: no neighbour boxes) of 2 to 100 random points
+    and one pair 2^-22 h apart at positions (i, j) of the box's point order, which
+    is the input order; the pairs cover every row and half-wavefront boundary of
+    the plan build's own-box test and random positions.  Returns (xyz, ids, q, k,
+    rows of the paired points)."""
+    rng = np.random.default_rng(seed)
+    h, k = 1.0 / 64, 2 * math.pi * 4
+    pts, rows, box, start = [], [], 0, 0
+    for s in [2, 3, 16, 17, 31, 32, 33, 47, 48, 63, 64, 65, 90, 100]:
+        pairs = {(0, 1), (0, s - 1), (s - 2, s - 1)}
+        for step in (1, 15, 16, 17, 31, 32, 33, 48, 64):
+            pairs |= {(i, i + step) for i in range(0, s - step, 7)}
+        while len(pairs) < min(60, s * (s - 1) // 2):
+            i, j = sorted(rng.choice(s, 2, replace=False))
+            pairs.add((int(i), int(j)))
+        for i, j in sorted(pairs):
+            cell = 3 * np.array([box % 32, box // 32 % 32, box // 1024])
+            p = (cell + rng.uniform(0.05, 0.95, (s, 3))) * h
+            u = rng.standard_normal(3)
+            p[j] = p[i] + h * 2.0 ** -22 * u / np.linalg.norm(u)
+            pts.append(p)
+            rows += [start + i, start + j]
+            start += s
+            box += 1
+    xyz = np.ascontiguousarray(np.concatenate(pts))
+    ids = W.leaf_ids(xyz, np.zeros(3), h)
+    q = W.strengths(xyz.shape[0], 1, rng, np.complex64)
+    return xyz, ids, q, k, np.array(rows)
+
+
+@pytest.mark.parametrize("layout", ["tiles", "csr"])
+def test_own_box_pair_at_every_lane_offset(layout):
+    # a box with no close neighbour box is marked for the close-pair path only by
+    # the plan build's test of its own points: a pair it missed would be summed
+    # from the fixed-point coordinates, 2^7 quanta apart, about 1e-2 off
+    xyz, ids, q, k, rows = lane_pairs()
+    print("lane pairs: %d points, %d boxes, %d paired rows" % (xyz.shape[0], W.count_boxes(ids), rows.size),
+          flush=True)
+    P = p2p.Plan(dev(xyz, torch.float64), dev(ids, torch.int32), k, dtype=torch.complex64, layout=layout)
+    y = P.apply(dev(q)).cpu().numpy().reshape(-1, 1)
+    P.close()
+    qq = q.astype(np.complex128)
+    yref = np.zeros((xyz.shape[0], 1), np.complex128)
+    for i in rows:
+        near, G, _, _ = near_terms(xyz, ids, k, i)
+        yref[i, 0] = G @ qq[near]
+    fw, _, _ = abs_row_sums(xyz, ids, k, rows, qq)
+    e_abs = err_over_abs(y, yref, rows, fw)
+    print("  %s: paired rows error / sum|terms| max %.2e" % (layout, e_abs.max()), flush=True)
+    assert e_abs.max() <= ABS_TOL

@@ -1,7 +1,9 @@
 """Plan and batch lifetime on the GPU: double destroy, device allocation failure
 (P2P_TEST_FAIL_ALLOC), destroy right after asynchronous work on another stream,
-positions that moved after the plan was built, and the autotuner cache read at
-plan creation."""
+builds, applies and releases enqueued without host waits (the build returns
+before its last kernels end, the release hands memory back behind the work that
+used it), a plan used on another stream right after its build, positions that
+moved after the plan was built, and the autotuner cache read at plan creation."""
 import math
 
 import numpy as np
@@ -80,10 +82,68 @@ def test_destroy_after_work_on_another_stream(inst):
         for _ in range(3):
             P = p2p.Plan(xyz, ids, inst.k, layout="csr")
             outs.append(P.apply(q))
-            P.close()  # waits for the apply just enqueued, then hands the memory back
+            P.close()  # hands the memory back behind the apply just enqueued
     torch.cuda.current_stream().wait_stream(s)
     for y in outs:
         assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def grid_tensors(inst):
+    return (dev(inst.xyz, torch.float64), [float(v) for v in inst.origin], inst.h,
+            dev(inst.q[:, 0].copy()))
+
+
+def test_steps_without_host_waits(inst):
+    # two geometries of different sizes in turn, so that each build takes blocks
+    # another plan released while its apply could still be running
+    other = W.sphere(26000, 16, 2 * math.pi * 6, seed=3, m=1, dtype=np.complex64)
+    geoms = [grid_tensors(inst), grid_tensors(other)]
+    ks = [inst.k, other.k]
+    refs = []
+    for g, k in zip(geoms, ks):
+        xyz, org, h, q = g
+        P = p2p.Plan.from_grid(xyz, org, h, k, layout="csr")
+        torch.cuda.synchronize()
+        refs.append(P.apply(q).cpu().numpy())
+        torch.cuda.synchronize()
+        P.close()
+        torch.cuda.synchronize()
+    outs = []
+    for step in range(12):
+        xyz, org, h, q = geoms[step % 2]
+        P = p2p.Plan.from_grid(xyz, org, h, ks[step % 2], layout="csr" if step % 4 < 2 else "tiles")
+        outs.append(P.apply(q))
+        P.close()
+    torch.cuda.synchronize()
+    for step, y in enumerate(outs):
+        assert np.array_equal(y.cpu().numpy(), refs[step % 2]), step
+
+
+def test_plan_used_on_another_stream_right_after_build(inst):
+    xyz, org, h, q = grid_tensors(inst)
+    P = p2p.Plan.from_grid(xyz, org, h, inst.k, layout="csr")
+    torch.cuda.synchronize()
+    ref = P.apply(q).cpu().numpy()
+    info_ref = P.info()
+    export_ref = P.export()
+    P.close()
+    s_build, s_use = torch.cuda.Stream(), torch.cuda.Stream()
+    s_build.wait_stream(torch.cuda.current_stream())
+    s_use.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        with torch.cuda.stream(s_build):
+            P = p2p.Plan.from_grid(xyz, org, h, inst.k, layout="csr")
+        if rep == 0:  # host reads of the plan right after the build
+            assert P.info() == info_ref
+            got = P.export()
+            assert all(np.array_equal(got[key], export_ref[key]) for key in export_ref)
+        with torch.cuda.stream(s_use):
+            y = P.apply(q)
+        s_use.synchronize()
+        assert np.array_equal(y.cpu().numpy(), ref), rep
+        with torch.cuda.stream(s_use):
+            P.close()
+    torch.cuda.synchronize()
 
 
 def test_moved_positions_are_rejected(inst):
