@@ -35,33 +35,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# VALU issue model of the MI355X, in issue slots of 128 FP32 lanes per clock per
+# CU (the published 157.3 TFLOP/s FP32 vector rate at 256 CUs and 2.4 GHz; plain,
+# unpacked v_fma_f32 reaches it, measured by the issue-rate microbenchmark at
+# about 100 lanes per clock per CU counted at 2.4 GHz).  Measured costs, in such
+# slots: FP32 FMA, multiply, add and integer operations 1, conversions 2,
+# transcendentals 4 (quarter rate), and a transcendental does not issue beside
+# the other VALU work: the microbenchmark's pair stream (15 FMAs, rsq, sin, cos)
+# takes the sum of its parts' times.
+CUS, LANES_PER_CLK, CLOCK_HZ = 256, 128, 2.4e9
+PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 7.86e13 issue slots / s
+
 # Algorithmic work per pair of the FP32 Helmholtz sweep: 3 coordinate differences,
 # 3 operations for r^2, r = r^2 / r, the phase in turns and its range reduction
 # (2), G = (cos, sin) / r (2) and the complex multiply-add (4): 15 VALU operations,
-# plus the transcendentals rsq, sin and cos.  Measured issue rates on the MI355X:
-# 64 lanes per clock per CU for FP32 VALU operations, 32 for transcendentals, so a
-# transcendental takes two issue slots: 21 slots per pair.
-SLOTS_PER_PAIR = 15 + 2 * 3
-CUS, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9
-PEAK_SLOTS = CUS * LANES_PER_CLK * CLOCK_HZ            # 3.93e13 issue slots / s
-PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 1872 Gpair/s
+# plus the transcendentals rsq, sin and cos at 4 slots each: 27 slots per pair.
+SLOTS_PER_PAIR = 15 + 4 * 3
+PEAK_GPAIRS = PEAK_SLOTS / SLOTS_PER_PAIR / 1e9        # 2913 Gpair/s
+ISSUE_LIB = os.path.join(ROOT, "paper_2403_01596_amd", "libp2p_issue.so")
+ISSUE_MIXES = ["fma", "trans", "pair", "issued", "int", "cvt"]
 
 # Reverse pass (dq and dx together, FP32 Helmholtz), per pair: the geometry above
 # (3 differences, 3 for r^2, r, phase and reduction: 9 VALU + rsq, sin, cos), G =
 # (c + is)/r (2), dq's conj(G) g (4), u = conj(g_i) q_j + conj(g_j) q_i (8), the two
 # parts of (c + is)(ik - 1/r) (2), Re(G' u) (2), 1/r^2 and its product (2) and the
-# three dx multiply-adds (3): 32 VALU operations plus 3 transcendentals = 38 issue
-# slots.
-BWD_SLOTS_PER_PAIR = 32 + 2 * 3
-PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 1034 Gpair/s
+# three dx multiply-adds (3): 32 VALU operations plus 3 transcendentals = 44 slots.
+BWD_SLOTS_PER_PAIR = 32 + 4 * 3
+PEAK_BWD_GPAIRS = PEAK_SLOTS / BWD_SLOTS_PER_PAIR / 1e9   # 1787 Gpair/s
 
 # FP64 sweep, per pair: 3 differences, 3 for r^2, the 1/r refinement (5), r and the
 # phase in turns (2), the half-turn reduction (3), x^2, x^4, x^8 (3), the sine and
 # cosine polynomials (20) and the sine's factor x (1), the sign of an odd half
 # turn (4) and its application (2), G (2) and the complex multiply-add (4): 52 FP64
-# VALU operations at one slot each (FP64 FMA measured at 49-53 lanes per clock per
-# CU) plus v_rsq_f64 at 16 lanes per clock, 4 slots: 56 issue slots.
-F64_SLOTS_PER_PAIR = 52 + 4
+# VALU operations at 64 lanes per clock per CU (the published 78.6 TFLOP/s FP64
+# vector rate: 2 of the slots above each) plus v_rsq_f64 at a quarter of that (8):
+# 112 slots.
+F64_SLOTS_PER_PAIR = 2 * 52 + 8
 PEAK_F64_GPAIRS = PEAK_SLOTS / F64_SLOTS_PER_PAIR / 1e9   # 702 Gpair/s
 
 # Multi-RHS product: one complex multiply-add per (pair, right-hand side) = 8 real
@@ -74,6 +83,7 @@ PEAK_MFMA_F32 = 157.3e12
 SPIN_UP_S = 0.25
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_counters.md")
+VALU_COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_f32_csr_sphere2M_valu_counters.md")
 KERNEL_SOURCES = ["paper_2403_01596_amd/csrc/sweep.h", "paper_2403_01596_amd/csrc/apply.hip",
                   "paper_2403_01596_amd/csrc/common.h"]
 MRHS_COUNTERS_FILE = os.path.join(ROOT, "profiles", "mrhs_f32_csr_batch17_counters.md")
@@ -142,6 +152,20 @@ def kernel_source_digest(sources=None) -> str:
     return h.hexdigest()[:16]
 
 
+def stored_value(path, key, sources=None):
+    """A figure (`key: value`) from a committed counter summary, if the summary was
+    taken on the current kernel sources (else None)."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"source_digest:\s*([0-9a-f]+)", text)
+    b = re.search(key + r":\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_digest(sources):
+        return None
+    return float(b.group(1))
+
+
 def stored_traffic(path=None, sources=None):
     """HBM bytes per launch of a kernel from its committed counter summary, if the
     summary was taken on the current kernel sources (else None)."""
@@ -154,6 +178,56 @@ def stored_traffic(path=None, sources=None):
     if not m or not b or m.group(1) != kernel_source_digest(sources):
         return None
     return float(b.group(1))
+
+
+def measure_issue_rates(torch, iters=4000, blocks=8 * CUS):
+    """VALU issue rates of six instruction mixes (libp2p_issue.so): FMA, the three
+    transcendentals, the FP32 sweep's algorithmic stream per pair (15 FMAs + rsq,
+    sin, cos), the mix the sweep issues per pair (its counters), integer
+    subtractions and conversions; 8 workgroups of 4 wavefronts per CU, every chain
+    independent.  Per mix: lane-operations per second, the lanes per clock per CU
+    that rate means at the published 2.4 GHz (a lower bound of the per-clock rate,
+    since the clock runs at most that fast), and the mix's time per operation in
+    FMA issue slots (FMA mix = 1)."""
+    import ctypes
+    L = ctypes.CDLL(ISSUE_LIB)
+    L.p2p_issue_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_float)]
+    L.p2p_issue_counts.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    lanes = blocks * 256.0 * iters  # loop trips of all lanes
+    out = {}
+    ms = ctypes.c_float()
+    fma_slot_ms = None
+    for mix, name in enumerate(ISSUE_MIXES):
+        valu, trans = ctypes.c_int(), ctypes.c_int()
+        L.p2p_issue_counts(mix, ctypes.byref(valu), ctypes.byref(trans))
+        end = time.perf_counter() + SPIN_UP_S  # the clock out of idle first
+        while time.perf_counter() < end:
+            rc = L.p2p_issue_run(mix, blocks, iters, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError("issue-rate kernel %s failed (%d)" % (name, rc))
+        times = []
+        for _ in range(5):
+            rc = L.p2p_issue_run(mix, blocks, iters, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError("issue-rate kernel %s failed (%d)" % (name, rc))
+            times.append(ms.value)
+        t_ms = min(times)
+        ops = lanes * valu.value
+        if fma_slot_ms is None:
+            fma_slot_ms = t_ms / valu.value  # the FMA mix comes first: its time per FMA per lane-trip
+        r = {"valu_per_trip": valu.value, "trans_per_trip": trans.value, "ms": round(t_ms, 4),
+             "lane_ops_per_s": float("%.4g" % (ops / (t_ms * 1e-3))),
+             "lanes_per_clk_cu_at_2_4ghz": round(ops / (t_ms * 1e-3) / CUS / CLOCK_HZ, 2),
+             "fma_slots_per_trip": round(t_ms / fma_slot_ms, 2)}
+        if name == "pair":
+            r["gpairs_s"] = round(lanes / (t_ms * 1e-3) / 1e9, 1)
+        out[name] = r
+        log("issue %-6s %2d VALU/trip (%2d transcendental): %.3f ms, %6.2f lanes/clk/CU at 2.4 GHz, "
+            "%5.2f FMA slots per trip" % (name, valu.value, trans.value, t_ms, r["lanes_per_clk_cu_at_2_4ghz"],
+                                          r["fma_slots_per_trip"]))
+    return out
 
 
 def measure_mrhs(p2p, W, torch, reps, with_oracle):
@@ -283,7 +357,8 @@ def measure_backward(p2p, W, torch, reps, with_oracle):
         plan.close()
     out["roofline_f32"] = {"bound": "alu", "achieved": out["f32"]["gpairs_s"], "peak": round(PEAK_BWD_GPAIRS, 1),
                            "unit": "Gpair/s", "frac": round(out["f32"]["gpairs_s"] / PEAK_BWD_GPAIRS, 4),
-                           "work_per_pair": "32 VALU + 3 transcendental = %d issue slots" % BWD_SLOTS_PER_PAIR}
+                           "work_per_pair": "32 VALU + 3 transcendental (4 slots each) = %d issue slots"
+                                            % BWD_SLOTS_PER_PAIR}
     log("backward: f32 %.3f ms (%.1f Gpair/s, %.1f%% of its ALU roofline), f64 %.3f ms" % (
         out["f32"]["kernel_ms"], out["f32"]["gpairs_s"], 100 * out["roofline_f32"]["frac"], out["f64"]["kernel_ms"]))
     return out
@@ -308,6 +383,7 @@ def measure_layouts(p2p, W, torch, reps, with_oracle):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             plan = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=layout)
+            torch.cuda.synchronize()  # the build returns before its last kernels end
             plan_ms = (time.perf_counter() - t0) * 1e3
             info = plan.info()
             n_pairs = info["n_pairs"]
@@ -325,7 +401,8 @@ def measure_layouts(p2p, W, torch, reps, with_oracle):
             kern_ms /= calls
             row[layout] = {"plan_ms": round(plan_ms, 3), "sweep_ms": round(kern_ms, 4),
                            "gpairs_s": round(n_pairs / kern_ms / 1e6, 2), "rel_err": err,
-                           "close_pairs": info["n_close_pairs"], "device_bytes": info["device_bytes"]}
+                           "close_pairs": info["n_close_pairs"], "near_boxes": info["n_near_boxes"],
+                           "boxes": info["n_boxes"], "device_bytes": info["device_bytes"]}
             plan.close()
         row["n_pairs"] = n_pairs
         out["D%d" % d] = row
@@ -415,6 +492,7 @@ def measure_paper_2d(p2p, torch, reps, with_oracle, max_layout_bytes=4e9, max_bo
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             P = p2p.Plan.from_grid(xd, (0.0, 0.0, 0.0), 2.0 ** (1 - level), 0.0, dtype=torch.complex128, layout="csr")
+            torch.cuda.synchronize()
             plan_ms = (time.perf_counter() - t0) * 1e3
             yo = torch.empty(N, dtype=torch.float64, device=dev)
             a_ms = kernel_ms(lambda: P.apply_log2d(qd, yo))
@@ -604,6 +682,8 @@ def main():
     ap.add_argument("--paper-2d-cell", default=None, metavar="L,i",
                     help="only the two 2-D layouts' kernels on one cell of that grid, 5 runs each "
                          "(for counter runs)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only the VALU issue-rate microbenchmark (one JSON line)")
     ap.add_argument("--overlap", action="store_true",
                     help="only the near field beside a far-field stand-in on a second stream")
     ap.add_argument("--backward-only", action="store_true",
@@ -634,6 +714,10 @@ def main():
 
     if args.overlap:
         print(json.dumps(measure_overlap(p2p, W, torch, 20)))
+        return 0
+
+    if args.issue_rates:
+        print(json.dumps(measure_issue_rates(torch)))
         return 0
 
     if args.paper_2d_cell:
@@ -712,37 +796,52 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # every timed step bracketed by HIP events on the stream the step runs on (the
-    # plan build's host waits show up as gaps between its kernels, so the events
-    # measure the step as the GPU sees it, waits included); the headline is the
-    # median step
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # the timed region: K steps back to back, bracketed by a synchronisation and a
+    # HIP event on the stream the steps run on at each end (the plan build's host
+    # waits show up as idle time inside it); the headline is the region over K
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record()
+    r0.record()
+    for _ in range(args.steps):
         y32 = step()
-        e1.record()
+    r1.record()
     torch.cuda.synchronize()
     wall_s = (time.perf_counter() - t0) / args.steps
+    step_s = r0.elapsed_time(r1) * 1e-3 / args.steps
+    # the spread of single steps: K more, an event pair around each.  Every event
+    # recorded behind the sweep costs GPU time of its own (measured: the idle spell
+    # between a sweep and the next build's first kernel grows from about 6 us to
+    # 40-60 us with the two per-step events), so these run above the region's mean.
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in evs])
-    step_s = float(np.median(step_ms)) * 1e-3
-    log("step: median %.3f ms, mean %.3f ms (events), %.3f ms (host clock)" % (
-        step_s * 1e3, step_ms.mean(), wall_s * 1e3))
+    log("step: %.3f ms (timed region / %d), %.3f ms (host clock); per-step events: median %.3f, min %.3f" % (
+        step_s * 1e3, args.steps, wall_s * 1e3, float(np.median(step_ms)), float(step_ms.min())))
 
-    # ---- where the step's time goes: each phase bracketed by synchronisations
+    # ---- where the step's time goes: one step at a time from an idle GPU, an event
+    # before the build, between build and apply, and after the apply (the build
+    # returns before its last kernels end, so the GPU's clock divides the phases);
+    # the release on the host clock
     phases = {"plan_create": 0.0, "apply": 0.0, "release": 0.0}
     for _ in range(args.steps):
+        ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        ea.record()
         pl = p2p.Plan.from_grid(xyz, origin, inst.h, inst.k, dtype=torch.complex64, layout=args.layout)
-        t2 = time.perf_counter()
+        eb.record()
         pl.apply(q32)
-        torch.cuda.synchronize()
+        ec.record()
         t3 = time.perf_counter()
         pl.close()
         t4 = time.perf_counter()
-        for key, dt in zip(phases, (t2 - t1, t3 - t2, t4 - t3)):
-            phases[key] += dt * 1e3 / args.steps
+        torch.cuda.synchronize()
+        for key, dt in zip(phases, (ea.elapsed_time(eb), eb.elapsed_time(ec), (t4 - t3) * 1e3)):
+            phases[key] += dt / args.steps
     log("phases (ms): " + ", ".join("%s %.3f" % kv for kv in phases.items()))
     # the box ids on their own (p2p_box_ids, one synchronisation), for comparison
     torch.cuda.synchronize()
@@ -756,6 +855,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan32 = p2p.Plan(xyz, ids, inst.k, dtype=torch.complex64, layout=args.layout)
+    torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     info = plan32.info()
     n_pairs = info["n_pairs"]
@@ -796,10 +896,18 @@ def main():
 
     achieved = n_pairs / (sweep32_ms * 1e-3) / 1e9
     traffic = stored_traffic() if args.layout == "csr" else None
+    issue = measure_issue_rates(torch)
+    issued = stored_value(VALU_COUNTERS_FILE, "issued_slots_per_pair") if args.layout == "csr" else None
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_GPAIRS, 1), "unit": "Gpair/s",
                 "frac": round(achieved / PEAK_GPAIRS, 4), "traffic": traffic,
                 "kernel": "sweep FP32 %s (k_apply<F32,helmholtz,%s>)" % (args.layout, args.layout),
-                "work_per_pair": "15 VALU + 3 transcendental = %d issue slots" % SLOTS_PER_PAIR,
+                "work_per_pair": "15 VALU (1 slot) + 3 transcendental (4 slots) = %d issue slots of 128 lanes/clk/CU"
+                                 % SLOTS_PER_PAIR,
+                "pair_stream_measured": {"gpairs_s": issue["pair"]["gpairs_s"],
+                                         "fma_slots_per_pair": issue["pair"]["fma_slots_per_trip"],
+                                         "fma_lanes_per_clk_cu_at_2_4ghz":
+                                             issue["fma"]["lanes_per_clk_cu_at_2_4ghz"]},
+                "algorithmic_slots_per_pair": SLOTS_PER_PAIR, "issued_slots_per_pair": issued,
                 "pairs_per_launch": n_pairs, "kernel_ms": round(sweep32_ms, 4)}
 
     # ---- oracle on the host cores: every target row of the same input
@@ -847,9 +955,13 @@ def main():
         "metric": "near-field interactions/s (G-pairs/s) at stated rel-err; % of VALU/HBM roofline",
         "value": round(value, 3), "unit": "Gpair/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "step_timing": {"statistic": "median of %d per-step HIP event intervals" % args.steps,
-                        "mean_ms": round(float(step_ms.mean()), 4), "min_ms": round(float(step_ms.min()), 4),
-                        "max_ms": round(float(step_ms.max()), 4), "host_clock_mean_ms": round(wall_s * 1e3, 4)},
+        "step_timing": {"statistic": "HIP events bracketing %d back-to-back steps, over %d" % (args.steps, args.steps),
+                        "host_clock_mean_ms": round(wall_s * 1e3, 4),
+                        "per_step_events": {"median_ms": round(float(np.median(step_ms)), 4),
+                                            "min_ms": round(float(step_ms.min()), 4),
+                                            "max_ms": round(float(step_ms.max()), 4),
+                                            "note": "an event pair around each of %d further steps; the events "
+                                                    "themselves add GPU time to each step" % args.steps}},
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": inst.name, "n_points": inst.n, "k": inst.k, "leaf_h": inst.h,
                    "d_mean": round(inst.d_mean, 3), "rhs": 1, "precision": "f32", "layout": args.layout,
@@ -866,7 +978,7 @@ def main():
                   "roofline_f64": {"bound": "alu", "achieved": round(n_pairs / sweep64_ms / 1e6, 2),
                                    "peak": round(PEAK_F64_GPAIRS, 1), "unit": "Gpair/s",
                                    "frac": round(n_pairs / sweep64_ms / 1e6 / PEAK_F64_GPAIRS, 4),
-                                   "work_per_pair": "52 FP64 VALU + v_rsq_f64 (4) = %d issue slots"
+                                   "work_per_pair": "52 FP64 VALU (2 slots) + v_rsq_f64 (8) = %d issue slots"
                                                     % F64_SLOTS_PER_PAIR}},
         "plan_ms": round(plan_s * 1e3, 3),
         "step_phases_ms": {k: round(v, 4) for k, v in phases.items()},
@@ -877,8 +989,10 @@ def main():
                           "bytes_per_point": "24 read (positions) + 40 written (permutation, FP64 and fixed-point "
                                              "coordinates) + 24 per box + 4 per neighbour-list entry"},
         "box_ids_call_ms": round(box_ids_ms, 4),
-        "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"]},
+        "plan": {"n_boxes": info["n_boxes"], "t_max": info["t_max"], "device_bytes": info["device_bytes"],
+                 "near_boxes": info["n_near_boxes"], "close_pairs": info["n_close_pairs"]},
         "roofline": roofline,
+        "issue_rates": issue,
         "cpu_baseline": cpu,
         "multi_rhs": mrhs,
         "backward": backward,

@@ -103,6 +103,9 @@ typedef struct {
                             FP64 coordinates; 0 for FP64 plans                     */
   int64_t n_targets;    /* plans of distinct sets (p2p_plan_create_st): targets, the
                            first n_targets of n_points; otherwise n_points         */
+  int64_t n_near_boxes; /* FP32 plans: boxes whose sweep checks every pair for the
+                           close-pair path (two own points within 2^20 quanta, or
+                           a neighbour's bounding box within reach); 0 for FP64  */
 } p2p_info;
 
 /* Leaf-box ids from positions: box_ijk[i][a] = floor((xyz[i][a] - origin[a]) / h),

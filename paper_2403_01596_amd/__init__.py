@@ -43,7 +43,7 @@ class _Info(ctypes.Structure):
                 ("n_slots", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_zero_pairs", ctypes.c_int64),
                 ("tile_entries", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("t_max", ctypes.c_int32),
                 ("quantum_exp", ctypes.c_int32), ("d_mean", ctypes.c_double), ("max_sep", ctypes.c_double),
-                ("n_close_pairs", ctypes.c_int64), ("n_targets", ctypes.c_int64)]
+                ("n_close_pairs", ctypes.c_int64), ("n_targets", ctypes.c_int64), ("n_near_boxes", ctypes.c_int64)]
 
 
 class _Info2D(ctypes.Structure):

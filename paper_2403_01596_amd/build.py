@@ -1,4 +1,5 @@
-"""Builds libp2p.so (the HIP library behind include/p2p.h) in-tree for gfx950.
+"""Builds libp2p.so (the HIP library behind include/p2p.h) in-tree for gfx950,
+and libp2p_issue.so, the VALU issue-rate microbenchmark the benchmark loads.
 
     python -m paper_2403_01596_amd.build
 
@@ -22,6 +23,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp2p.so")
 SOURCES = ["api.hip", "memory.hip", "plan.hip", "apply.hip", "backward.hip", "mrhs.hip", "batch.hip",
            "quad2d.hip"]
+ISSUE_SOURCES = ["issue_rates.hip"]
+ISSUE_LIB = os.path.join(HERE, "libp2p_issue.so")
 ARCH = os.environ.get("P2P_OFFLOAD_ARCH", "gfx950")
 
 
@@ -55,16 +58,21 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build() -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+def _link(objs, lib: str) -> None:
     tl = torch_lib_dir()
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = ["g++", "-shared", "-o", tmp] + objs + ["-L" + tl, "-l:libamdhip64.so", "-Wl,-rpath," + tl,
                                                   "-Wl,--no-undefined"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        objs = list(ex.map(_compile, SOURCES + ISSUE_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], ISSUE_LIB)
     return LIB
 
 

@@ -216,6 +216,7 @@ p2p_status create_plan(const double* xyz, const int32_t* box_ijk, const p2p::Gri
   P->n_pairs = -1;
   P->n_zero = -1;
   P->n_close = -1;
+  P->n_near = -1;
   P->timed = new (std::nothrow) std::vector<std::pair<hipEvent_t, hipEvent_t>>();
   if (!P->timed) {
     delete P;
@@ -346,6 +347,7 @@ p2p_status p2p_plan_info(p2p_plan plan, p2p_info* out) {
   out->max_sep = plan->max_sep;
   out->n_close_pairs = plan->n_close;
   out->n_targets = plan->n_targets;
+  out->n_near_boxes = plan->n_near;
   return P2P_OK;
 }
 

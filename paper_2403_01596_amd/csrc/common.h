@@ -90,6 +90,7 @@ struct p2p_plan_s {
   int64_t n_targets;
   int32_t* src_start;  // [B + 1]
   int64_t n_close;     // ordered near pairs closer than kCloseQuanta quanta, -1 until counted
+  int64_t n_near;      // boxes marked near (FP32 plans), counted with n_close
   // scratch for apply/backward: strengths and upstream gradients in sorted order
   void* q_sorted;      // [n * max_rhs] complex
   void* g_sorted;      // [n * max_rhs] complex

@@ -412,6 +412,7 @@ struct DevStatus {
   uint64_t maxabs;     // bits of the largest |coordinate|
   uint64_t zero;       // zero-distance pairs (statistics only)
   uint64_t ncp;        // FP32 plans: close pairs (statistics only)
+  uint64_t nnear;      // FP32 plans: boxes marked near (statistics only)
 };
 
 constexpr uint32_t kIdMask = (1u << kIdBits) - 1;
@@ -1657,6 +1658,18 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   return P2P_OK;
 }
 
+// The number of nonzero entries of a[0..n), added to *out (one atomic per
+// workgroup).
+__global__ void __launch_bounds__(kBlock) k_count_nonzero(const int32_t* __restrict__ a, int64_t n,
+                                                       unsigned long long* __restrict__ out) {
+  __shared__ uint64_t lds[kWavesPerBlockPlan];
+  uint64_t c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    c += a[i] != 0 ? 1u : 0u;
+  c = block_combine63((uint64_t)wave_add63(c), lds, [](uint64_t x, uint64_t y) { return x + y; });
+  if (threadIdx.x == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
 p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   if (P->n_pairs >= 0) return P2P_OK;
   ScopedBlock blk(s);
@@ -1676,6 +1689,8 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
       hipLaunchKernelGGL(k_count_close, dim3(g), dim3(kBlock), 0, s, P->sx32, P->sx64, P->n, P->box_start,
                          src_begin(P), tgt_end(P), P->nbr_start, P->nbr_idx, P->near, (int32_t)P->B, part);
       hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(kBlock), 0, s, part, (int64_t)g, &status->ncp);
+      hipLaunchKernelGGL(k_count_nonzero, dim3((unsigned)std::min<int64_t>(256, grid_for(P->B))), dim3(kBlock), 0, s,
+                         P->near, (int64_t)P->B, (unsigned long long*)&status->nnear);
     }
   }
   P2P_HIP(hipGetLastError());
@@ -1685,6 +1700,7 @@ p2p_status count_pairs(p2p_plan_s* P, hipStream_t s) {
   P->n_zero = (int64_t)hs.zero;
   P->n_pairs = P->n_slots - P->n_zero;
   P->n_close = (int64_t)hs.ncp;
+  P->n_near = (int64_t)hs.nnear;
   return P2P_OK;
 }
 
