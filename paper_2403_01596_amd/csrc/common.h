@@ -71,7 +71,8 @@ struct p2p_plan_s {
   // geometry, sorted order
   double* sx64;        // [3][n] FP64 coordinates (SoA)
   int32_t* sx32;       // [3][n] fixed-point coordinates, low 32 bits (FP32 plans)
-  // replicated per-box source lists (TILES)
+  // replicated per-box source lists (TILES); the offsets are kept for both layouts
+  // (CSR sweeps take each box's list length from them)
   int32_t* tile_start; // [B+1]
   int32_t* tile_src;   // [tile_len] sorted position of the source
   double* tile_x64;    // [3][tile_len] (FP64 plans)

@@ -521,16 +521,13 @@ __device__ __forceinline__ void sweep(const SweepGeom<Tr>& G, const Op& op, Swee
   // the box's own sources, first in its neighbourhood list; a target's own entry
   // (its self pair) is entry t + so of the list, with one point set only
   const int32_t n_own = ld_uniform(G.box_start + T + 1) - ld_uniform(G.src_begin + T);
-  int32_t s0 = 0, s1 = 0;
+  // the box's neighbourhood list: entries [s0, s1) of the replicated lists (TILES),
+  // or [0, s1) numbered from the box's own sources on (CSR; the plan keeps the
+  // offsets of the replicated lists for both layouts)
+  int32_t s0 = ld_uniform(G.tile_start + T), s1 = ld_uniform(G.tile_start + T + 1);
   if (CSR) {
-    const int32_t j1 = ld_uniform(G.nbr_start + T + 1);
-    for (int32_t j = ld_uniform(G.nbr_start + T); j < j1; ++j) {
-      const int32_t S = ld_uniform(G.nbr_idx + j);
-      s1 += ld_uniform(G.box_start + S + 1) - ld_uniform(G.src_begin + S);
-    }
-  } else {
-    s0 = ld_uniform(G.tile_start + T);
-    s1 = ld_uniform(G.tile_start + T + 1);
+    s1 -= s0;
+    s0 = 0;
   }
   const int64_t n = G.n, tl = G.tl;
   const bool near_box = G.near != nullptr && ld_uniform(G.near + T) != 0;
