@@ -87,18 +87,30 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(ScanIO<T> io, int64_t n,
   if (threadIdx.x == 0) io.part[y][blockIdx.x] = tot;
 }
 
+// One workgroup per array: the exclusive prefix sums of its g partial sums, each
+// thread taking kScanItems consecutive ones per round (a round's loads all in
+// flight at once; up to kScanTile partials, 2^22 scanned elements, take one round).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_scan_partials(ScanIO<T> io, int64_t g) {
   __shared__ T lds[kBlock / kWave];
   const int y = blockIdx.y;
   T* __restrict__ part = io.part[y];
   T carry = 0;
-  for (int64_t c = 0; c < g; c += kBlock) {
-    int64_t e = c + threadIdx.x;
-    T v = e < g ? part[e] : T(0);
+  for (int64_t c = 0; c < g; c += kScanTile) {
+    const int64_t base = c + (int64_t)threadIdx.x * kScanItems;
+    T v[kScanItems], sum = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      v[r] = base + r < g ? part[base + r] : T(0);
+      sum += v[r];
+    }
     T tot;
-    T ex = block_exclusive_scan<T>(v, lds, &tot);
-    if (e < g) part[e] = ex + carry;
+    T ex = block_exclusive_scan<T>(sum, lds, &tot) + carry;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+      if (base + r < g) part[base + r] = ex;
+      ex += v[r];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0 && io.total[y]) *io.total[y] = carry;
@@ -448,12 +460,19 @@ __device__ __forceinline__ void fold_into(Partial& a, const Partial& p) {
   a.maxabs = fmax(a.maxabs, p.maxabs);
 }
 
-// One workgroup: every thread folds a stride of rows, then a tree over the threads.
-__global__ void __launch_bounds__(kBlock) k_fold(const Partial* __restrict__ part, int rows,
-                                              DevStatus* __restrict__ status) {
+// One workgroup folds the kGridStride partial rows: every thread kFoldRows of them,
+// all loaded before the first fold (one after another, each load's latency had
+// been the kernel's time), then a tree over the threads.
+constexpr int kFoldRows = kGridStride / kBlock;
+static_assert(kFoldRows * kBlock == kGridStride, "partial rows must fill the fold's threads");
+__global__ void __launch_bounds__(kBlock) k_fold(const Partial* __restrict__ part, DevStatus* __restrict__ status) {
   __shared__ Partial acc[kBlock];
-  Partial a{};
-  for (int r = threadIdx.x; r < rows; r += kBlock) fold_into(a, part[r]);
+  Partial b[kFoldRows];
+#pragma unroll
+  for (int i = 0; i < kFoldRows; ++i) b[i] = part[i * kBlock + threadIdx.x];
+  Partial a = b[0];
+#pragma unroll
+  for (int i = 1; i < kFoldRows; ++i) fold_into(a, b[i]);
   acc[threadIdx.x] = a;
   __syncthreads();
   for (int half = kBlock / 2; half > 0; half >>= 1) {
@@ -1471,7 +1490,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   else
     hipLaunchKernelGGL(k_keys<false>, dim3(gk), dim3(kBlock), 0, s, ids, nullptr, GridSpec{{0, 0, 0}, 1.0}, n, k0,
                        part);
-  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, status);
   P2P_HIP(hipGetLastError());
   // The first radix pass does not depend on what the copy reports, so it is
   // enqueued behind it and runs while the host waits: it assumes keys of at most
@@ -1565,7 +1584,7 @@ p2p_status build_plan(p2p_plan_s* P, const double* xyz, const int32_t* ids, cons
   //         the offsets of the B boxes and, at index B, the totals.
   hipLaunchKernelGGL(k_nbr<false>, dim3(gs), dim3(kBlock), 0, s, P->box_key, P->box_start, bb, status, grid, cnt, src,
                      nullptr, nullptr, part, nullptr, nullptr, n, 0, nullptr, 0.0, src_begin(P), tgt_end(P));
-  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, kGridStride, status);
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kBlock), 0, s, part, status);
   P2P_HIP(hipGetLastError());
   {  // both box-indexed arrays in one set of launches (partu is free once the sort is done)
     const ScanIO<int32_t> io{{cnt, src}, {P->nbr_start, P->tile_start}, {part32, (int32_t*)partu},
