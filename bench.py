@@ -677,6 +677,8 @@ def main():
                     help="only build the plan and run the apply --apply-reps times (for counter runs)")
     ap.add_argument("--sweep-precision", choices=["f32", "f64"], default="f32",
                     help="precision of the plan that --sweep-only runs")
+    ap.add_argument("--sweep-workload", choices=["sphere2M", "ellipsoid4M_D16", "ellipsoid4M_D32", "ellipsoid4M_D64"],
+                    default="sphere2M", help="input of --sweep-only")
     ap.add_argument("--paper-2d", action="store_true",
                     help="only the paper's 2-D experiment grid (Indexing vs Repetition) and the model re-fit")
     ap.add_argument("--paper-2d-cell", default=None, metavar="L,i",
@@ -762,7 +764,10 @@ def main():
             plan.close()
         return 0
 
-    inst = W.sphere_2m()
+    if args.sweep_only and args.sweep_workload != "sphere2M":
+        inst = W.ellipsoid_4m(int(args.sweep_workload.split("_D")[1]))
+    else:
+        inst = W.sphere_2m()
     log("workload %s: n=%d h=%.6g D=%.2f k=%.4f" % (inst.name, inst.n, inst.h, inst.d_mean, inst.k))
     xyz = torch.from_numpy(inst.xyz).to(dev)
     q32 = torch.from_numpy(inst.q[:, 0].copy()).to(dev)
